@@ -1,0 +1,196 @@
+/*
+ * libnep — neuroevolution-potential (NEP) training hot path on AMD Instinct
+ * MI355X (gfx950): batched descriptors, energies, forces and virials over many
+ * periodic structures, the weighted energy/force/virial loss, its analytic
+ * gradient with respect to every parameter, and the Adam/AMSGrad update.
+ *
+ * The operations follow the TorchNEP paper (arXiv 2606.19557):
+ *   site energies Eq. (1); descriptor scaling Eq. (2); per-species network
+ *   Eq. (3); loss Eqs. (4)-(7); gradient g_t = dL/dtheta and Adam/AMSGrad
+ *   Eqs. (8)-(13); radial descriptor Eqs. (15)-(16); Chebyshev basis with
+ *   cosine cutoff Eqs. (17)-(18); angular moments Eq. (19); three-body
+ *   invariant Eq. (20); 4-body and 5-body contractions of the moments
+ *   (Methods, "NEP descriptors").
+ *
+ * Conventions (all entry points):
+ *   - Every array argument is a DEVICE pointer owned by the caller unless the
+ *     comment says "host". The library keeps no pointer after a call returns
+ *     and allocates no device memory: temporaries live in the caller's
+ *     workspace `ws` of `ws_bytes` bytes (size from nep_workspace_size).
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *     is the default stream), except nep_build_neighbors, which synchronises
+ *     the stream once to learn the pair count.
+ *   - Return value: NEP_OK (0) or a negative nep_status. Arguments are
+ *     validated on the host before anything is launched; on error nothing is
+ *     written and nep_last_error() (thread-local) describes the problem.
+ *   - dtype selects the bulk floating-point type of positions, pair vectors,
+ *     forces, parameters, gradients, descriptors and scaler: NEP_F32 or
+ *     NEP_F64. Energies, virials, loss values and loss seeds are always double.
+ *   - Layouts are row-major and densely packed.
+ *
+ * Parameter vector theta (length from nep_param_count), in this order:
+ *   c_R[a][b][n][k]  (T*T*(n_max_r+1)*(basis_r+1))  radial coefficients, Eq. (16),
+ *                    a = species of the centre atom, b = species of the neighbour;
+ *   c_A[a][b][n][k]  (T*T*(n_max_a+1)*(basis_a+1))  angular coefficients, Eq. (19);
+ *   for each species t: W0[t][mu][nu] (H*D), b0[t][mu] (H), w1[t][mu] (H), Eq. (3);
+ *   b1               (1) shared output bias, Eq. (3).
+ * Descriptor vector q (length D): radial n = 0..n_max_r; then for l = 1..l_max
+ * and n = 0..n_max_a the three-body q_nl = sum_m A_nlm^2 (real orthonormal
+ * harmonics); then, if l_max_4b = 2, q4_n (n = 0..n_max_a), the (2 2 2)
+ * Wigner-3j contraction of the complex l = 2 moments; then, if l_max_5b = 1,
+ * q5_n = (sum_m A_n1m^2)^2.
+ */
+#ifndef NEP_H
+#define NEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nep_status;
+
+enum {
+    NEP_OK = 0,
+    NEP_ERR_INVALID_ARG = -1, /* null pointer, negative size, inconsistent sizes */
+    NEP_ERR_UNSUPPORTED = -2, /* model shape without a compiled kernel, rc_a > rc_r, ... */
+    NEP_ERR_CAPACITY = -3,    /* neighbour buffer too small; required counts reported */
+    NEP_ERR_WORKSPACE = -4,   /* workspace smaller than nep_workspace_size */
+    NEP_ERR_HIP = -5          /* a HIP runtime call failed; message in nep_last_error */
+};
+
+enum { NEP_F32 = 0, NEP_F64 = 1 };
+
+/* Model hyper-parameters (the model keys of the paper's input file, Table I). */
+typedef struct {
+    int32_t num_types;  /* T >= 1 species */
+    int32_t n_max_r;    /* radial channels n = 0..n_max_r */
+    int32_t n_max_a;    /* angular channels n = 0..n_max_a */
+    int32_t basis_r;    /* Chebyshev functions k = 0..basis_r (radial) */
+    int32_t basis_a;    /* Chebyshev functions k = 0..basis_a (angular) */
+    int32_t l_max;      /* three-body harmonics l = 1..l_max */
+    int32_t l_max_4b;   /* 0 (off) or 2 (4-body term on) */
+    int32_t l_max_5b;   /* 0 (off) or 1 (5-body term on) */
+    int32_t hidden;     /* neurons H of the hidden layer */
+    int32_t dtype;      /* NEP_F32 or NEP_F64 */
+    double rc_r;        /* radial cutoff (Angstrom) */
+    double rc_a;        /* angular cutoff, 0 < rc_a <= rc_r */
+} nep_model;
+
+/* A packed batch of fully periodic structures. Structure s owns atoms
+ * atom_offset[s] .. atom_offset[s+1]-1; every structure has at least one atom. */
+typedef struct {
+    int32_t num_structures;     /* Ns >= 0 */
+    int64_t num_atoms;          /* Na = atom_offset[Ns] */
+    const int64_t* atom_offset; /* [Ns+1], atom_offset[0] = 0, non-decreasing */
+    const void* positions;      /* [Na][3] dtype, Cartesian Angstrom, any image */
+    const int32_t* types;       /* [Na] species in [0, T) */
+    const double* cells;        /* [Ns][3][3] rows = cell vectors a, b, c */
+} nep_batch;
+
+/* Neighbour lists (caller-allocated, filled by nep_build_neighbors).
+ * Row i holds every (j, image) with |r_ij| < rc_r, r_ij = r_j + n.H - r_i.
+ * The row is grouped by neighbour species b = 0..T-1; inside each group the
+ * pairs with |r_ij| < rc_a come first. */
+typedef struct {
+    int64_t capacity;         /* pairs `pairs` can hold */
+    int64_t* row_offset;      /* [Na+1] first pair of each row */
+    int32_t* seg_count;       /* [Na][T][2]: {pairs, angular pairs} per neighbour species */
+    void* pairs;              /* [capacity][4] dtype: r_ij x, y, z and the neighbour index j
+                                 stored bit-for-bit in the 4th slot (int32 in float, int64 in double) */
+    int32_t* atom_struct;     /* [Na] structure index of each atom */
+    int32_t* species_order;   /* [Na] atoms sorted by species (stable) */
+    int64_t* species_offset;  /* [T+1] start of each species in species_order */
+    int64_t num_pairs;        /* host, written by nep_build_neighbors (also on NEP_ERR_CAPACITY) */
+    int64_t num_angular_pairs;/* host, written by nep_build_neighbors */
+} nep_neighbors;
+
+/* Reference data and loss weights, Eqs. (4)-(7). */
+typedef struct {
+    const double* energy;       /* [Ns] target energies */
+    const void* force;          /* [Na][3] dtype target forces */
+    const double* virial;       /* [Ns][9] target virials */
+    const uint8_t* has_virial;  /* [Ns] 1 = structure has a virial label, or NULL = all labelled */
+    double lambda_e, lambda_f, lambda_v;
+} nep_targets;
+
+typedef struct {
+    double lr, beta1, beta2, eps; /* paper defaults 0.9, 0.999, 1e-8 */
+    int32_t amsgrad;              /* 1 = keep the running maximum, 0 = plain Adam */
+    int32_t amsgrad_mode;         /* 0 = maximum of the bias-corrected second moment (Eq. 12);
+                                     1 = maximum of the raw second moment, then bias correction
+                                     (the torch.optim.Adam form) */
+} nep_adam_cfg;
+
+/* Number of parameters P and descriptor length D (host outputs). Pure host call. */
+nep_status nep_param_count(const nep_model* model, int64_t* num_params, int64_t* num_descriptors);
+
+/* Workspace bytes (host output) for any call on a batch of Ns structures, Na
+ * atoms and num_pairs neighbour pairs (use nep_neighbors.num_pairs). Pure host. */
+nep_status nep_workspace_size(const nep_model* model, int32_t num_structures, int64_t num_atoms,
+                              int64_t num_pairs, size_t* bytes);
+
+/* Builds the neighbour lists of a batch (once per dataset; the paper keeps
+ * them on the GPU, Results, "Training efficiency"). Cutoffs from the model.
+ * On NEP_ERR_CAPACITY nbr->num_pairs holds the required pair count; grow
+ * nbr->pairs and call again. ws must hold nep_workspace_size(..., 0) bytes. */
+nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, nep_neighbors* nbr, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* Energies E_s = sum_i E_i (Eq. 1), forces F_k = -dE/dr_k and virials
+ * W_s = -sum_{i in s, j} r_ij (x) dE_i/dr_ij (9 components, row-major).
+ *   theta   [P] dtype; q_scale [D] dtype (Eq. 2 factors 1/(q_max - q_min));
+ *   energy  [Ns] double (required); force [Na][3] dtype or NULL;
+ *   virial  [Ns][9] double or NULL; descriptor [Na][D] dtype or NULL (unscaled q). */
+nep_status nep_forward(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                       const nep_neighbors* nbr, double* energy, void* force, double* virial, void* descriptor,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* The weighted loss L = lambda_e Delta_E + lambda_f Delta_F + lambda_v Delta_V
+ * (Eqs. 4-7; N_s, N_a, N_a^s over the batch; Delta_V over labelled structures)
+ * and its gradient dL/dtheta (the g_t of Adam, Eq. 8), computed analytically.
+ *   loss [4] double device: {L, Delta_E, Delta_F, Delta_V};
+ *   grad [P] dtype, overwritten;
+ *   energy [Ns] double, force [Na][3] dtype, virial [Ns][9] double: optional
+ *   prediction outputs (NULL = not returned). */
+nep_status nep_loss_and_grad(const nep_model* model, const void* theta, const void* q_scale,
+                             const nep_batch* batch, const nep_neighbors* nbr, const nep_targets* targets,
+                             double* loss, void* grad, double* energy, void* force, double* virial, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of (E, F, W) with respect to theta:
+ *   grad = sum_s dE[s] dE_s/dtheta + sum_i dF[i] . dF_i/dtheta + sum_s dW[s] : dW_s/dtheta.
+ *   dE [Ns] double, dF [Na][3] dtype, dW [Ns][9] double (any may be NULL = zero);
+ *   grad [P] dtype, overwritten. */
+nep_status nep_backward(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                        const nep_neighbors* nbr, const double* dE, const void* dF, const double* dW, void* grad,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam/AMSGrad step t (1-based) of Eqs. (8)-(13), in place on theta, m, v,
+ * vmax (all [P] of dtype; vmax unused when cfg->amsgrad = 0, may be NULL). */
+nep_status nep_adam_step(int64_t num_params, int32_t dtype, void* theta, const void* grad, void* m, void* v,
+                         void* vmax, int64_t t, const nep_adam_cfg* cfg, void* stream);
+
+/* Eq. (2) factors from descriptors: q_scale[nu] = 1/(max_i q[i][nu] - min_i q[i][nu]),
+ * or 1 where that range is below 1e-10. descriptor [Na][D], q_scale [D], dtype. */
+nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int32_t dtype, const void* descriptor,
+                                void* q_scale, void* stream);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* nep_last_error(void);
+
+/* Per-kernel timing with HIP events (for measurement only; adds a small cost).
+ * nep_profile_enable(1) starts recording every launch of every later call on
+ * its stream; nep_profile_read synchronises, then copies up to `cap` entries
+ * (host arrays) of kernel name, launch count and total milliseconds, and
+ * returns the number of distinct kernels in *count. enable(0) stops and clears. */
+nep_status nep_profile_enable(int32_t on);
+nep_status nep_profile_read(int32_t cap, char (*names)[64], int64_t* launches, double* total_ms, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEP_H */

@@ -1,0 +1,450 @@
+// C-ABI entry points of libnep: host-side validation, workspace layout,
+// dispatch to the per-shape pipelines, Adam, the scaler, error reporting and
+// optional per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nep_internal.hpp"
+#include "nep_reduce.hpp"
+
+namespace nep {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local char g_err[512] = {0};
+
+nep_status fail(nep_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+// --------------------------------------------------------------- profiling
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec*> g_prof;
+
+bool profiling_on() { return g_prof_on; }
+
+void profile_begin(const char* name, hipStream_t st, void** token) {
+    ProfRec* r = new ProfRec{name, nullptr, nullptr};
+    if (hipEventCreate(&r->a) != hipSuccess || hipEventCreate(&r->b) != hipSuccess) {
+        delete r;
+        *token = nullptr;
+        return;
+    }
+    (void)hipEventRecord(r->a, st);
+    *token = r;
+}
+
+void profile_end(void* token, hipStream_t st) {
+    ProfRec* r = static_cast<ProfRec*>(token);
+    (void)hipEventRecord(r->b, st);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back(r);
+}
+
+static void profile_clear() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (ProfRec* r : g_prof) {
+        (void)hipEventDestroy(r->a);
+        (void)hipEventDestroy(r->b);
+        delete r;
+    }
+    g_prof.clear();
+}
+
+// ------------------------------------------------------------------ shapes
+
+#define NEP_SHAPE(KR, KA, NR, NA, L, H4, H5)                              \
+    nep_status shape_f32_##KR##_##KA##_##NR##_##NA##_##L##_##H4##_##H5(const Ctx&); \
+    nep_status shape_f64_##KR##_##KA##_##NR##_##NA##_##L##_##H4##_##H5(const Ctx&);
+#include "nep_shapes.inc"
+#undef NEP_SHAPE
+
+static const ShapeEntry g_shapes[] = {
+#define NEP_SHAPE(KR, KA, NR, NA, L, H4, H5)                                            \
+    {KR, KA, NR, NA, L, H4, H5, shape_f32_##KR##_##KA##_##NR##_##NA##_##L##_##H4##_##H5, \
+     shape_f64_##KR##_##KA##_##NR##_##NA##_##L##_##H4##_##H5},
+#include "nep_shapes.inc"
+#undef NEP_SHAPE
+};
+
+const ShapeEntry* shape_table(int* count) {
+    *count = int(sizeof(g_shapes) / sizeof(g_shapes[0]));
+    return g_shapes;
+}
+
+const ShapeEntry* find_shape(const Dims& d) {
+    int n = 0;
+    const ShapeEntry* t = shape_table(&n);
+    for (int k = 0; k < n; ++k)
+        if (t[k].KR == d.KR && t[k].KA == d.KA && t[k].NR == d.NR && t[k].NA == d.NA && t[k].L == d.L &&
+            t[k].H4 == d.has4 && t[k].H5 == d.has5)
+            return &t[k];
+    return nullptr;
+}
+
+// ---------------------------------------------------------------- layout
+
+static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const Dims& dm, bool f64, int Ns, long Na) {
+    Layout L{};
+    const size_t r = f64 ? 8 : 4;
+    const size_t na = size_t(Na > 0 ? Na : 0), ns = size_t(Ns > 0 ? Ns : 0);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    L.nbr_totals = take(2 * sizeof(int64_t));
+    L.q = take(r * na * dm.D);
+    L.A = take(r * na * dm.NA * dm.LM);
+    L.S0 = take(r * na * dm.T * dm.KR);
+    L.S1 = take(r * na * dm.T * dm.KR);
+    L.Eat = take(r * na);
+    L.e = take(r * na * dm.D);
+    L.t = take(r * na * dm.H);
+    L.B = take(r * na * dm.NA * dm.LM);
+    L.eps = take(r * na * dm.T * dm.KR);
+    L.F = take(r * na * 3);
+    L.Wat = take(r * na * 9);
+    L.ubar = take(r * na * 3);
+    L.dq = take(r * na * dm.D);
+    L.dA = take(r * na * dm.NA * dm.LM);
+    L.abar = take(r * na * dm.D);
+    L.alpha = take(r * na * dm.H);
+    L.beta = take(r * na * dm.H);
+    L.gam = take(r * na * dm.H);
+    L.Bp = take(r * na * dm.NA * dm.LM);
+    L.Es = take(8 * ns);
+    L.Ws = take(8 * ns * 9);
+    L.ebar = take(8 * ns);
+    L.Ubar = take(8 * ns * 9);
+    L.lossp = take(8 * ns * 3);
+    const long tiles = (Na + kBlock / kTeam - 1) / (kBlock / kTeam);
+    L.ang_rows = int(tiles < kMaxAngRows ? tiles : kMaxAngRows);
+    if (L.ang_rows < 1) L.ang_rows = 1;
+    L.outer_chunk = kOuterChunk;
+    const long chunks = (Na + kOuterChunk - 1) / kOuterChunk;
+    L.outer_rows = int(chunks < kMaxOuterRows ? chunks : kMaxOuterRows);
+    if (L.outer_rows < 1) L.outer_rows = 1;
+    const size_t rowlen = size_t(dm.offA) + size_t(dm.offB1 - dm.offN);
+    L.outer_part = take(8 * rowlen * size_t(L.outer_rows));
+    L.ang_part = take(8 * size_t(dm.offN - dm.offA) * size_t(L.ang_rows));
+    L.total = o;
+    return L;
+}
+
+// ------------------------------------------------------------ validation
+
+static nep_status make_dims(const nep_model* m, Dims* d) {
+    if (!m) return fail(NEP_ERR_INVALID_ARG, "model is NULL");
+    if (m->num_types < 1 || m->num_types > kMaxTypes)
+        return fail(NEP_ERR_UNSUPPORTED, "num_types %d outside [1, %d]", m->num_types, kMaxTypes);
+    if (m->n_max_r < 0 || m->n_max_a < 0 || m->basis_r < 0 || m->basis_a < 0 || m->hidden < 1)
+        return fail(NEP_ERR_INVALID_ARG, "negative n_max/basis or hidden < 1");
+    if (m->l_max < 1 || m->l_max > 4) return fail(NEP_ERR_UNSUPPORTED, "l_max %d outside [1, 4]", m->l_max);
+    if (m->l_max_4b != 0 && m->l_max_4b != 2) return fail(NEP_ERR_UNSUPPORTED, "l_max_4b must be 0 or 2");
+    if (m->l_max_5b != 0 && m->l_max_5b != 1) return fail(NEP_ERR_UNSUPPORTED, "l_max_5b must be 0 or 1");
+    if (m->l_max_4b == 2 && m->l_max < 2) return fail(NEP_ERR_UNSUPPORTED, "4-body term needs l_max >= 2");
+    if (m->dtype != NEP_F32 && m->dtype != NEP_F64) return fail(NEP_ERR_INVALID_ARG, "dtype %d", m->dtype);
+    if (!(m->rc_a > 0.0) || !std::isfinite(m->rc_r) || !(m->rc_a <= m->rc_r))
+        return fail(NEP_ERR_UNSUPPORTED, "cutoffs must satisfy 0 < rc_a <= rc_r (got %g, %g)", m->rc_a, m->rc_r);
+    d->T = m->num_types;
+    d->H = m->hidden;
+    d->NR = m->n_max_r + 1;
+    d->NA = m->n_max_a + 1;
+    d->KR = m->basis_r + 1;
+    d->KA = m->basis_a + 1;
+    d->L = m->l_max;
+    d->LM = (d->L + 1) * (d->L + 1) - 1;
+    d->has4 = m->l_max_4b == 2;
+    d->has5 = m->l_max_5b == 1;
+    d->D = d->NR + d->NA * (d->L + d->has4 + d->has5);
+    d->offA = long(d->T) * d->T * d->NR * d->KR;
+    d->offN = d->offA + long(d->T) * d->T * d->NA * d->KA;
+    d->offB1 = d->offN + long(d->T) * (d->D + 2) * d->H;
+    d->P = d->offB1 + 1;
+    d->rcR = m->rc_r;
+    d->rcA = m->rc_a;
+    return NEP_OK;
+}
+
+static nep_status check_batch(const nep_batch* b) {
+    if (!b) return fail(NEP_ERR_INVALID_ARG, "batch is NULL");
+    if (b->num_structures < 0 || b->num_atoms < 0) return fail(NEP_ERR_INVALID_ARG, "negative batch sizes");
+    if (b->num_atoms >= (int64_t(1) << 31) - 1) return fail(NEP_ERR_UNSUPPORTED, "more than 2^31-2 atoms");
+    if (!b->atom_offset) return fail(NEP_ERR_INVALID_ARG, "atom_offset is NULL");
+    if (b->num_atoms > 0 && b->num_structures == 0) return fail(NEP_ERR_INVALID_ARG, "atoms without structures");
+    if (b->num_atoms > 0 && (!b->positions || !b->types)) return fail(NEP_ERR_INVALID_ARG, "positions/types NULL");
+    if (b->num_structures > 0 && !b->cells) return fail(NEP_ERR_INVALID_ARG, "cells is NULL");
+    return NEP_OK;
+}
+
+static nep_status check_nbr(const nep_neighbors* n, const nep_batch* b) {
+    if (!n) return fail(NEP_ERR_INVALID_ARG, "neighbors is NULL");
+    if (!n->row_offset || !n->seg_count || !n->atom_struct || !n->species_order || !n->species_offset)
+        return fail(NEP_ERR_INVALID_ARG, "a neighbour array is NULL");
+    if (n->num_pairs < 0 || n->num_pairs > n->capacity)
+        return fail(NEP_ERR_INVALID_ARG, "neighbour list not built (num_pairs %lld, capacity %lld)",
+                    (long long)n->num_pairs, (long long)n->capacity);
+    if (n->num_pairs > 0 && !n->pairs) return fail(NEP_ERR_INVALID_ARG, "pairs is NULL");
+    (void)b;
+    return NEP_OK;
+}
+
+static nep_status base_ctx(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                           const nep_neighbors* nbr, void* ws, size_t ws_bytes, void* stream, Mode mode, Ctx* c,
+                           const ShapeEntry** se) {
+    clear_error();
+    std::memset(c, 0, sizeof(*c));
+    nep_status s;
+    if ((s = make_dims(model, &c->dm))) return s;
+    if ((s = check_batch(batch))) return s;
+    if ((s = check_nbr(nbr, batch))) return s;
+    if (!theta) return fail(NEP_ERR_INVALID_ARG, "theta is NULL");
+    if (mode != Mode::Descriptors && !q_scale) return fail(NEP_ERR_INVALID_ARG, "q_scale is NULL");
+    *se = find_shape(c->dm);
+    if (!*se)
+        return fail(NEP_ERR_UNSUPPORTED,
+                    "no compiled kernel for n_max %d/%d, basis %d/%d, l_max %d %d %d",
+                    model->n_max_r, model->n_max_a, model->basis_r, model->basis_a, model->l_max, model->l_max_4b,
+                    model->l_max_5b);
+    c->f64 = model->dtype == NEP_F64;
+    const size_t shm = (c->f64 ? 8 : 4) * size_t(c->dm.T) * c->dm.T * c->dm.NA * c->dm.KA;
+    if (shm > 64 * 1024) return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block too large for LDS (%zu bytes)", shm);
+    c->stream = static_cast<hipStream_t>(stream);
+    c->mode = mode;
+    c->Ns = batch->num_structures;
+    c->Na = long(batch->num_atoms);
+    c->pairs = nbr->num_pairs;
+    c->atom_offset = batch->atom_offset;
+    c->types = batch->types;
+    c->row = nbr->row_offset;
+    c->seg = nbr->seg_count;
+    c->pair_data = nbr->pairs;
+    c->atom_struct = nbr->atom_struct;
+    c->species_order = nbr->species_order;
+    c->theta = theta;
+    c->qscale = q_scale;
+    if (!ws) return fail(NEP_ERR_INVALID_ARG, "workspace is NULL");
+    c->ws = static_cast<unsigned char*>(ws);
+    c->ws_bytes = ws_bytes;
+    return NEP_OK;
+}
+
+static nep_status dispatch(const Ctx& c, const ShapeEntry* se) { return c.f64 ? se->f64(c) : se->f32(c); }
+
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" {
+
+const char* nep_last_error(void) { return g_err; }
+
+nep_status nep_param_count(const nep_model* model, int64_t* num_params, int64_t* num_descriptors) {
+    clear_error();
+    Dims d;
+    nep_status s = make_dims(model, &d);
+    if (s) return s;
+    if (!num_params || !num_descriptors) return fail(NEP_ERR_INVALID_ARG, "output pointer is NULL");
+    *num_params = d.P;
+    *num_descriptors = d.D;
+    return NEP_OK;
+}
+
+nep_status nep_workspace_size(const nep_model* model, int32_t num_structures, int64_t num_atoms, int64_t num_pairs,
+                              size_t* bytes) {
+    clear_error();
+    Dims d;
+    nep_status s = make_dims(model, &d);
+    if (s) return s;
+    if (!bytes || num_structures < 0 || num_atoms < 0 || num_pairs < 0)
+        return fail(NEP_ERR_INVALID_ARG, "bad workspace query");
+    *bytes = make_layout(d, model->dtype == NEP_F64, num_structures, long(num_atoms)).total;
+    return NEP_OK;
+}
+
+nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, nep_neighbors* nbr, void* ws,
+                               size_t ws_bytes, void* stream) {
+    clear_error();
+    Ctx c;
+    std::memset(&c, 0, sizeof(c));
+    nep_status s;
+    if ((s = make_dims(model, &c.dm))) return s;
+    if ((s = check_batch(batch))) return s;
+    if (!nbr || !nbr->row_offset || !nbr->seg_count || !nbr->atom_struct || !nbr->species_order ||
+        !nbr->species_offset)
+        return fail(NEP_ERR_INVALID_ARG, "a neighbour array is NULL");
+    if (nbr->capacity < 0 || (nbr->capacity > 0 && !nbr->pairs))
+        return fail(NEP_ERR_INVALID_ARG, "bad pair capacity or buffer");
+    if (!ws) return fail(NEP_ERR_INVALID_ARG, "workspace is NULL");
+    c.f64 = model->dtype == NEP_F64;
+    c.stream = static_cast<hipStream_t>(stream);
+    nbr->num_pairs = -1;
+    nbr->num_angular_pairs = -1;
+    return build_neighbors(c, batch, nbr, ws, ws_bytes);
+}
+
+nep_status nep_forward(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                       const nep_neighbors* nbr, double* energy, void* force, double* virial, void* descriptor,
+                       void* ws, size_t ws_bytes, void* stream) {
+    Ctx c;
+    const ShapeEntry* se = nullptr;
+    const bool only_desc = !energy && !force && !virial && descriptor;
+    nep_status s = base_ctx(model, theta, q_scale, batch, nbr, ws, ws_bytes, stream,
+                            only_desc ? Mode::Descriptors : Mode::Forward, &c, &se);
+    if (s) return s;
+    if (!only_desc && !energy) return fail(NEP_ERR_INVALID_ARG, "energy output is NULL");
+    c.E_out = energy;
+    c.F_out = force;
+    c.W_out = virial;
+    c.desc_out = descriptor;
+    return dispatch(c, se);
+}
+
+nep_status nep_loss_and_grad(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                             const nep_neighbors* nbr, const nep_targets* tg, double* loss, void* grad, double* energy,
+                             void* force, double* virial, void* ws, size_t ws_bytes, void* stream) {
+    Ctx c;
+    const ShapeEntry* se = nullptr;
+    nep_status s = base_ctx(model, theta, q_scale, batch, nbr, ws, ws_bytes, stream, Mode::LossGrad, &c, &se);
+    if (s) return s;
+    if (!tg || !loss || !grad) return fail(NEP_ERR_INVALID_ARG, "targets, loss or grad is NULL");
+    if (batch->num_structures > 0 && (!tg->energy || !tg->virial))
+        return fail(NEP_ERR_INVALID_ARG, "target energy/virial is NULL");
+    if (batch->num_atoms > 0 && !tg->force) return fail(NEP_ERR_INVALID_ARG, "target force is NULL");
+    if (!std::isfinite(tg->lambda_e) || !std::isfinite(tg->lambda_f) || !std::isfinite(tg->lambda_v))
+        return fail(NEP_ERR_INVALID_ARG, "loss weights must be finite");
+    c.Et = tg->energy;
+    c.Ft = tg->force;
+    c.Wt = tg->virial;
+    c.has_v = tg->has_virial;
+    c.lam_e = tg->lambda_e;
+    c.lam_f = tg->lambda_f;
+    c.lam_v = tg->lambda_v;
+    c.loss = loss;
+    c.grad = grad;
+    c.E_out = energy;
+    c.F_out = force;
+    c.W_out = virial;
+    return dispatch(c, se);
+}
+
+nep_status nep_backward(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                        const nep_neighbors* nbr, const double* dE, const void* dF, const double* dW, void* grad,
+                        void* ws, size_t ws_bytes, void* stream) {
+    Ctx c;
+    const ShapeEntry* se = nullptr;
+    nep_status s = base_ctx(model, theta, q_scale, batch, nbr, ws, ws_bytes, stream, Mode::Backward, &c, &se);
+    if (s) return s;
+    if (!grad) return fail(NEP_ERR_INVALID_ARG, "grad is NULL");
+    c.dE = dE;
+    c.dF = dF;
+    c.dW = dW;
+    c.grad = grad;
+    return dispatch(c, se);
+}
+
+nep_status nep_adam_step(int64_t num_params, int32_t dtype, void* theta, const void* grad, void* m, void* v,
+                         void* vmax, int64_t t, const nep_adam_cfg* cfg, void* stream) {
+    clear_error();
+    if (num_params < 0 || t < 1 || !cfg) return fail(NEP_ERR_INVALID_ARG, "bad Adam arguments (P %lld, t %lld)",
+                                                     (long long)num_params, (long long)t);
+    if (dtype != NEP_F32 && dtype != NEP_F64) return fail(NEP_ERR_INVALID_ARG, "dtype %d", dtype);
+    if (num_params == 0) return NEP_OK;
+    if (!theta || !grad || !m || !v || (cfg->amsgrad && !vmax)) return fail(NEP_ERR_INVALID_ARG, "NULL Adam array");
+    if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0 && cfg->beta2 >= 0.0 && cfg->beta2 < 1.0 && cfg->eps >= 0.0))
+        return fail(NEP_ERR_INVALID_ARG, "Adam constants out of range");
+    const double bc1 = 1.0 - std::pow(cfg->beta1, double(t)), bc2 = 1.0 - std::pow(cfg->beta2, double(t));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = int((num_params + kRedBlock - 1) / kRedBlock);
+    if (dtype == NEP_F64) {
+        NEP_LAUNCH("adam", (k_adam<double>), dim3(grid), dim3(kRedBlock), 0, st, long(num_params),
+                   static_cast<double*>(theta), static_cast<const double*>(grad), static_cast<double*>(m),
+                   static_cast<double*>(v), static_cast<double*>(vmax), cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, bc1,
+                   bc2, cfg->amsgrad, cfg->amsgrad_mode);
+    } else {
+        NEP_LAUNCH("adam", (k_adam<float>), dim3(grid), dim3(kRedBlock), 0, st, long(num_params),
+                   static_cast<float*>(theta), static_cast<const float*>(grad), static_cast<float*>(m),
+                   static_cast<float*>(v), static_cast<float*>(vmax), cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, bc1,
+                   bc2, cfg->amsgrad, cfg->amsgrad_mode);
+    }
+    return NEP_OK;
+}
+
+nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int32_t dtype, const void* descriptor,
+                                void* q_scale, void* stream) {
+    clear_error();
+    if (num_atoms < 0 || num_descriptors < 0) return fail(NEP_ERR_INVALID_ARG, "negative sizes");
+    if (dtype != NEP_F32 && dtype != NEP_F64) return fail(NEP_ERR_INVALID_ARG, "dtype %d", dtype);
+    if (num_descriptors == 0) return NEP_OK;
+    if (!q_scale || (num_atoms > 0 && !descriptor)) return fail(NEP_ERR_INVALID_ARG, "NULL array");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == NEP_F64)
+        NEP_LAUNCH("scale", (k_scale<double>), dim3(int(num_descriptors)), dim3(kRedBlock), 0, st, long(num_atoms),
+                   int(num_descriptors), static_cast<const double*>(descriptor), static_cast<double*>(q_scale));
+    else
+        NEP_LAUNCH("scale", (k_scale<float>), dim3(int(num_descriptors)), dim3(kRedBlock), 0, st, long(num_atoms),
+                   int(num_descriptors), static_cast<const float*>(descriptor), static_cast<float*>(q_scale));
+    return NEP_OK;
+}
+
+nep_status nep_profile_enable(int32_t on) {
+    clear_error();
+    if (!on) profile_clear();
+    g_prof_on = on != 0;
+    return NEP_OK;
+}
+
+nep_status nep_profile_read(int32_t cap, char (*names)[64], int64_t* launches, double* total_ms, int32_t* count) {
+    clear_error();
+    if (!count || cap < 0 || (cap > 0 && (!names || !launches || !total_ms)))
+        return fail(NEP_ERR_INVALID_ARG, "bad profile_read arguments");
+    std::map<std::string, std::pair<int64_t, double>> agg;
+    std::vector<std::string> order;
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        for (ProfRec* r : g_prof) {
+            if (hipEventSynchronize(r->b) != hipSuccess) return fail(NEP_ERR_HIP, "event synchronise failed");
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r->a, r->b) != hipSuccess) return fail(NEP_ERR_HIP, "event timing failed");
+            if (!agg.count(r->name)) order.push_back(r->name);
+            agg[r->name].first += 1;
+            agg[r->name].second += ms;
+        }
+    }
+    int k = 0;
+    for (const std::string& n : order) {
+        if (k < cap) {
+            std::snprintf(names[k], 64, "%s", n.c_str());
+            launches[k] = agg[n].first;
+            total_ms[k] = agg[n].second;
+        }
+        ++k;
+    }
+    *count = k;
+    return NEP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+// Device building blocks of the NEP kernels for gfx950: model dimensions,
+// the neighbour-pair record, the Chebyshev basis with cosine cutoff,
+// real solid harmonics up to l = 4 evaluated on value / directional-derivative
+// / gradient number types, the 4-body algebra on the l = 2 moments, and
+// team (sub-wavefront) reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nep {
+
+// Threads per block of the atom and pair-sweep kernels.
+constexpr int kBlock = 256;
+
+// Runtime model dimensions (host computes, kernels take by value).
+struct Dims {
+    int T, H, D;
+    int NR, NA, KR, KA, L, LM;
+    int has4, has5;
+    long offA, offN, offB1, P;
+    double rcR, rcA;
+};
+
+// Compile-time shape of the descriptor; every pair-sweep kernel is
+// instantiated for one shape so all per-lane arrays live in registers.
+template <int KR_, int KA_, int NR_, int NA_, int L_, int H4_, int H5_>
+struct Shape {
+    static constexpr int KR = KR_, KA = KA_, NR = NR_, NA = NA_, L = L_;
+    static constexpr bool H4 = H4_ != 0, H5 = H5_ != 0;
+    static constexpr int LM = (L + 1) * (L + 1) - 1;
+    static constexpr int D = NR + NA * (L + (H4 ? 1 : 0) + (H5 ? 1 : 0));
+    static_assert(L >= 1 && L <= 4, "solid harmonics are written out for l <= 4");
+    static_assert(!H4 || L >= 2, "4-body term needs l = 2 moments");
+};
+
+// One neighbour pair: r_ij and the neighbour index j, bit-cast into the 4th slot.
+template <typename R>
+struct alignas(4 * sizeof(R)) Rec {
+    R x, y, z, w;
+};
+
+__device__ __forceinline__ int rec_j(const Rec<float>& r) { return __float_as_int(r.w); }
+__device__ __forceinline__ int rec_j(const Rec<double>& r) { return (int)__double_as_longlong(r.w); }
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_(R x);
+template <>
+__device__ __forceinline__ float rsqrt_<float>(float x) { return 1.0f / sqrtf(x); }
+template <>
+__device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename R>
+__device__ __forceinline__ void sincospi_(R x, R* s, R* c);
+template <>
+__device__ __forceinline__ void sincospi_<float>(float x, float* s, float* c) { sincospif(x, s, c); }
+template <>
+__device__ __forceinline__ void sincospi_<double>(double x, double* s, double* c) { sincospi(x, s, c); }
+
+template <typename R>
+__device__ __forceinline__ R tanh_(R x);
+template <>
+__device__ __forceinline__ float tanh_<float>(float x) { return tanhf(x); }
+template <>
+__device__ __forceinline__ double tanh_<double>(double x) { return tanh(x); }
+
+// f_k(r) = (T_k(x) + 1)/2 f_c(r) with x = 2(r/rc - 1)^2 - 1 and
+// f_c = (cos(pi r/rc) + 1)/2 (Eqs. 17-18); zero at and beyond rc.
+// With D set, also f_k'(r), via T'_{k+1} = 2 T_k + 2x T'_k - T'_{k-1}.
+template <typename R, int K, bool DERIV>
+__device__ __forceinline__ void cheb_basis(R r, R rc, R inv_rc, R* f, R* fp) {
+    const R y = r * inv_rc - R(1);
+    const R x = R(2) * y * y - R(1);
+    R s, c;
+    sincospi_<R>(r * inv_rc, &s, &c);
+    const bool in = r < rc;
+    const R fc = in ? R(0.5) * (c + R(1)) : R(0);
+    const R fcp = in ? R(-0.5 * 3.14159265358979323846) * inv_rc * s : R(0);
+    const R xp = R(4) * y * inv_rc;
+    R t0 = R(1), t1 = x, d0 = R(0), d1 = R(1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const R tk = (k == 0) ? t0 : t1;
+        const R dk = (k == 0) ? d0 : d1;
+        f[k] = R(0.5) * (tk + R(1)) * fc;
+        if (DERIV) fp[k] = R(0.5) * (dk * xp * fc + (tk + R(1)) * fcp);
+        if (k >= 1) {
+            const R t2 = R(2) * x * t1 - t0;
+            const R d2 = R(2) * t1 + R(2) * x * d1 - d0;
+            t0 = t1;
+            t1 = t2;
+            d0 = d1;
+            d1 = d2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- number types
+
+// Value and one directional derivative.
+template <typename R>
+struct D1 {
+    R v, d;
+};
+template <typename R>
+__device__ __forceinline__ D1<R> operator+(D1<R> a, D1<R> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename R>
+__device__ __forceinline__ D1<R> operator-(D1<R> a, D1<R> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename R>
+__device__ __forceinline__ D1<R> operator*(D1<R> a, D1<R> b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
+template <typename R>
+__device__ __forceinline__ D1<R> operator*(R s, D1<R> a) { return {s * a.v, s * a.d}; }
+
+// Value and full gradient.
+template <typename R>
+struct G3 {
+    R v, x, y, z;
+};
+template <typename R>
+__device__ __forceinline__ G3<R> operator+(G3<R> a, G3<R> b) { return {a.v + b.v, a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename R>
+__device__ __forceinline__ G3<R> operator-(G3<R> a, G3<R> b) { return {a.v - b.v, a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename R>
+__device__ __forceinline__ G3<R> operator*(G3<R> a, G3<R> b) {
+    return {a.v * b.v, a.v * b.x + a.x * b.v, a.v * b.y + a.y * b.v, a.v * b.z + a.z * b.v};
+}
+template <typename R>
+__device__ __forceinline__ G3<R> operator*(R s, G3<R> a) { return {s * a.v, s * a.x, s * a.y, s * a.z}; }
+
+// Real orthonormal solid harmonics R_lm(x, y, z), homogeneous of degree l,
+// equal to Y_lm on the unit sphere; order l = 1..L, m = -l..l.
+// N is any number type with +, -, * and scalar multiplication.
+template <typename N, typename R, int L>
+__device__ __forceinline__ void solid_harmonics(const N& x, const N& y, const N& z, N* Y) {
+    constexpr double C1 = 0.4886025119029199;
+    constexpr double C2A = 1.0925484305920792, C20 = 0.31539156525252005, C22 = 0.5462742152960396;
+    constexpr double C33 = 0.5900435899266435, C32 = 2.890611442640554, C31 = 0.4570457994644658;
+    constexpr double C30 = 0.3731763325901154, C32B = 1.445305721320277;
+    constexpr double C44 = 2.5033429417967046, C43 = 1.7701307697799304, C42 = 0.9461746957575601;
+    constexpr double C41 = 0.6690465435572892, C40 = 0.10578554691520431, C42B = 0.47308734787878004;
+    constexpr double C44B = 0.6258357354491761;
+    Y[0] = R(C1) * y;
+    Y[1] = R(C1) * z;
+    Y[2] = R(C1) * x;
+    if (L < 2) return;
+    const N x2 = x * x, y2 = y * y, z2 = z * z, xy = x * y, xz = x * z, yz = y * z;
+    const N x2my2 = x2 - y2, x2py2 = x2 + y2;
+    Y[3] = R(C2A) * xy;
+    Y[4] = R(C2A) * yz;
+    Y[5] = R(C20) * (R(2) * z2 - x2py2);
+    Y[6] = R(C2A) * xz;
+    Y[7] = R(C22) * x2my2;
+    if (L < 3) return;
+    const N t3 = R(4) * z2 - x2py2;  // 5z^2 - r^2
+    Y[8] = R(C33) * (y * (R(3) * x2 - y2));
+    Y[9] = R(C32) * (xy * z);
+    Y[10] = R(C31) * (y * t3);
+    Y[11] = R(C30) * (z * (R(2) * z2 - R(3) * x2py2));
+    Y[12] = R(C31) * (x * t3);
+    Y[13] = R(C32B) * (z * x2my2);
+    Y[14] = R(C33) * (x * (x2 - R(3) * y2));
+    if (L < 4) return;
+    const N t42 = R(6) * z2 - x2py2;              // 7z^2 - r^2
+    const N t41 = R(4) * z2 - R(3) * x2py2;       // 7z^2 - 3r^2
+    const N r2 = x2py2 + z2;
+    Y[15] = R(C44) * (xy * x2my2);
+    Y[16] = R(C43) * (yz * (R(3) * x2 - y2));
+    Y[17] = R(C42) * (xy * t42);
+    Y[18] = R(C41) * (yz * t41);
+    Y[19] = R(C40) * (R(35) * (z2 * z2) - R(30) * (z2 * r2) + R(3) * (r2 * r2));
+    Y[20] = R(C41) * (xz * t41);
+    Y[21] = R(C42B) * (x2my2 * t42);
+    Y[22] = R(C43) * (xz * (x2 - R(3) * y2));
+    Y[23] = R(C44B) * (x2 * (x2 - R(3) * y2) - y2 * (R(3) * x2 - y2));
+}
+
+template <int LM>
+__device__ __forceinline__ constexpr int lm_degree(int lm) {
+    return lm < 3 ? 1 : lm < 8 ? 2 : lm < 15 ? 3 : 4;
+}
+
+// ------------------------------------------------------------------ 4-body
+
+// Symmetric traceless 3x3 matrix S = sum_j g_j (u_j u_j^T - I/3) rebuilt from
+// the real l = 2 moments a[m+2] of the solid harmonics above.
+template <typename R>
+struct Sym3 {
+    R xx, yy, zz, xy, xz, yz;
+};
+
+template <typename R>
+__device__ __forceinline__ Sym3<R> sym_from_l2(const R* a) {
+    constexpr double C2A = 1.0925484305920792, C20 = 0.31539156525252005, C22 = 0.5462742152960396;
+    Sym3<R> s;
+    s.xy = a[0] * R(1.0 / C2A);
+    s.yz = a[1] * R(1.0 / C2A);
+    s.zz = a[2] * R(1.0 / (3.0 * C20));
+    s.xz = a[3] * R(1.0 / C2A);
+    const R d = a[4] * R(1.0 / C22);
+    s.xx = R(0.5) * (d - s.zz);
+    s.yy = R(0.5) * (-d - s.zz);
+    return s;
+}
+
+// Adjoint of sym_from_l2: out[m] = <X, dS/da_m> (Frobenius) for symmetric X.
+template <typename R>
+__device__ __forceinline__ void l2_from_sym_adj(const Sym3<R>& X, R* out) {
+    constexpr double C2A = 1.0925484305920792, C20 = 0.31539156525252005, C22 = 0.5462742152960396;
+    out[0] = R(2.0 / C2A) * X.xy;
+    out[1] = R(2.0 / C2A) * X.yz;
+    out[2] = R(1.0 / (3.0 * C20)) * X.zz - R(1.0 / (6.0 * C20)) * (X.xx + X.yy);
+    out[3] = R(2.0 / C2A) * X.xz;
+    out[4] = R(1.0 / (2.0 * C22)) * (X.xx - X.yy);
+}
+
+// A B + B A for symmetric A, B.
+template <typename R>
+__device__ __forceinline__ Sym3<R> sym_anticomm(const Sym3<R>& A, const Sym3<R>& B) {
+    Sym3<R> o;
+    o.xx = R(2) * (A.xx * B.xx + A.xy * B.xy + A.xz * B.xz);
+    o.yy = R(2) * (A.xy * B.xy + A.yy * B.yy + A.yz * B.yz);
+    o.zz = R(2) * (A.xz * B.xz + A.yz * B.yz + A.zz * B.zz);
+    o.xy = A.xx * B.xy + A.xy * B.yy + A.xz * B.yz + B.xx * A.xy + B.xy * A.yy + B.xz * A.yz;
+    o.xz = A.xx * B.xz + A.xy * B.yz + A.xz * B.zz + B.xx * A.xz + B.xy * A.yz + B.xz * A.zz;
+    o.yz = A.xy * B.xz + A.yy * B.yz + A.yz * B.zz + B.xy * A.xz + B.yy * A.yz + B.yz * A.zz;
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ R sym_det(const Sym3<R>& s) {
+    return s.xx * (s.yy * s.zz - s.yz * s.yz) - s.xy * (s.xy * s.zz - s.yz * s.xz) + s.xz * (s.xy * s.yz - s.yy * s.xz);
+}
+
+// kappa such that the (2 2 2) Wigner-3j contraction of the complex l = 2
+// moments equals kappa tr(S^3): fixed by one neighbour along z, where the
+// contraction is (2 2 2; 0 0 0)(5/4pi)^(3/2) g^3 and tr(S^3) = 2 g^3 / 9.
+constexpr double KAPPA4 = -0.26998130975990764;
+
+// q4 = kappa tr(S^3) = 3 kappa det(S) for traceless S.
+template <typename R>
+__device__ __forceinline__ R q4_value(const R* a) {
+    return R(3.0 * KAPPA4) * sym_det(sym_from_l2(a));
+}
+// dq4/da = 3 kappa M*(S^2).
+template <typename R>
+__device__ __forceinline__ void q4_grad(const R* a, R* g) {
+    const Sym3<R> S = sym_from_l2(a);
+    Sym3<R> S2 = sym_anticomm(S, S);  // 2 S^2
+    l2_from_sym_adj(S2, g);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) g[m] *= R(1.5 * KAPPA4);
+}
+// d(dq4)/da along da: 3 kappa M*(S dS + dS S).
+template <typename R>
+__device__ __forceinline__ void q4_hess_vec(const R* a, const R* da, R* out) {
+    const Sym3<R> S = sym_from_l2(a), dS = sym_from_l2(da);
+    l2_from_sym_adj(sym_anticomm(S, dS), out);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) out[m] *= R(3.0 * KAPPA4);
+}
+
+// ------------------------------------------------------------ team reduce
+
+// Sum over the S consecutive lanes of a team (S a power of two <= 64).
+template <int S, typename R>
+__device__ __forceinline__ R team_sum(R v) {
+#pragma unroll
+    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace nep

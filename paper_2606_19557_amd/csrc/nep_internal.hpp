@@ -1,0 +1,115 @@
+// Host-side internals shared by the library's translation units: call
+// context, error reporting, launch wrapper with optional event timing, the
+// workspace layout, and the per-shape pipeline entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/nep.h"
+#include "nep_device.hpp"
+
+namespace nep {
+
+constexpr int kMaxTypes = 16;
+
+nep_status fail(nep_status code, const char* fmt, ...);
+void clear_error();
+
+// Event timing of launches (nep_profile_enable).
+bool profiling_on();
+void profile_begin(const char* name, hipStream_t st, void** token);
+void profile_end(void* token, hipStream_t st);
+
+#define NEP_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t _e = (call);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return ::nep::fail(NEP_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+#define NEP_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                                       \
+    do {                                                                                                \
+        void* _tok = nullptr;                                                                           \
+        if (::nep::profiling_on()) ::nep::profile_begin(name, stream, &_tok);                           \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
+        hipError_t _e = hipGetLastError();                                                              \
+        if (_tok) ::nep::profile_end(_tok, stream);                                                     \
+        if (_e != hipSuccess)                                                                           \
+            return ::nep::fail(NEP_ERR_HIP, "launch of %s failed: %s", name, hipGetErrorString(_e));    \
+    } while (0)
+
+enum class Mode { Descriptors, Forward, LossGrad, Backward };
+
+// Everything one call needs, already validated.
+struct Ctx {
+    Dims dm;
+    bool f64;
+    hipStream_t stream;
+    Mode mode;
+    int Ns;
+    long Na;
+    long pairs;
+    // batch / neighbours
+    const int64_t* atom_offset;
+    const int* types;
+    const int64_t* row;
+    const int* seg;
+    const void* pair_data;
+    const int* atom_struct;
+    const int* species_order;
+    // parameters
+    const void* theta;
+    const void* qscale;
+    // targets (LossGrad) or seeds (Backward)
+    const double* Et;
+    const void* Ft;
+    const double* Wt;
+    const uint8_t* has_v;
+    double lam_e, lam_f, lam_v;
+    const double* dE;
+    const void* dF;
+    const double* dW;
+    // outputs
+    double* loss;
+    void* grad;
+    double* E_out;
+    void* F_out;
+    double* W_out;
+    void* desc_out;
+    // workspace
+    unsigned char* ws;
+    size_t ws_bytes;
+};
+
+// Workspace carve-up (byte offsets), identical for every shape of given sizes.
+struct Layout {
+    size_t q, A, S0, S1, Eat, e, t, B, eps, F, Wat, ubar, dq, dA, abar, alpha, beta, gam, Bp;
+    size_t Es, Ws, ebar, Ubar, lossp, outer_part, ang_part, nbr_totals;
+    size_t total;
+    int outer_rows, ang_rows, outer_chunk;
+};
+
+Layout make_layout(const Dims& dm, bool f64, int Ns, long Na);
+
+// Team size (lanes per atom) of the pair sweeps and the grid caps.
+constexpr int kTeam = 8;
+constexpr int kMaxAngRows = 2048;
+constexpr int kMaxOuterRows = 1024;
+constexpr int kOuterChunk = 256;
+
+// Per-shape pipeline (forward / loss+grad / backward / descriptors).
+using ShapeFn = nep_status (*)(const Ctx&);
+struct ShapeEntry {
+    int KR, KA, NR, NA, L, H4, H5;
+    ShapeFn f32, f64;
+};
+const ShapeEntry* find_shape(const Dims& dm);
+const ShapeEntry* shape_table(int* count);
+
+nep_status build_neighbors(const Ctx& c, const nep_batch* b, nep_neighbors* nb, void* ws, size_t ws_bytes);
+
+}  // namespace nep

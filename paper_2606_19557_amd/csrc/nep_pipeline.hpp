@@ -1,0 +1,96 @@
+// The launch sequence of one call for one descriptor shape and precision.
+//
+//   descriptors : descriptor
+//   forward     : descriptor -> network_forward -> force -> structure
+//   loss+grad   : forward, structure(loss, seeds) -> tangent -> network_backward
+//                 -> angular_coeff_grad -> outer_grad -> final_reduce
+//   backward    : descriptor -> network_forward -> seeds -> tangent -> ... -> final_reduce
+#pragma once
+
+#include "nep_internal.hpp"
+#include "nep_kernels.hpp"
+#include "nep_reduce.hpp"
+
+namespace nep {
+
+template <typename R, class Sh>
+nep_status run_shape(const Ctx& c) {
+    const Layout L = make_layout(c.dm, c.f64, c.Ns, c.Na);
+    if (c.ws_bytes < L.total) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, %zu needed", c.ws_bytes, L.total);
+    auto Wr = [&](size_t off) { return reinterpret_cast<R*>(c.ws + off); };
+    auto Wd = [&](size_t off) { return reinterpret_cast<double*>(c.ws + off); };
+    const Dims dm = c.dm;
+    const hipStream_t st = c.stream;
+    const int Na = int(c.Na);
+    const R* theta = static_cast<const R*>(c.theta);
+    const R* qscale = static_cast<const R*>(c.qscale);
+    const Rec<R>* pairs = static_cast<const Rec<R>*>(c.pair_data);
+    constexpr int S = kTeam;
+    const int team_grid = (Na + kBlock / S - 1) / (kBlock / S);
+    const int atom_grid = (Na + kBlock - 1) / kBlock;
+
+    R* q = (c.mode == Mode::Descriptors || c.desc_out) && c.desc_out ? static_cast<R*>(c.desc_out) : Wr(L.q);
+    if (Na > 0)
+        NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types,
+                   Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0));
+    if (c.mode == Mode::Descriptors) return NEP_OK;
+
+    if (Na > 0)
+        NEP_LAUNCH("network_forward", (k_network_forward<R, Sh>), dim3(atom_grid), dim3(kBlock), 0, st, dm, theta,
+                   qscale, c.types, Na, q, Wr(L.A), Wr(L.Eat), Wr(L.e), Wr(L.t), Wr(L.B), Wr(L.eps));
+
+    double* Es = c.E_out ? c.E_out : Wd(L.Es);
+    double* Ws = c.W_out ? c.W_out : Wd(L.Ws);
+    R* F = c.F_out ? static_cast<R*>(c.F_out) : Wr(L.F);
+    const bool loss = c.mode == Mode::LossGrad;
+
+    if (c.mode == Mode::Forward || loss) {
+        if (Na > 0)
+            NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types, Na,
+                       c.row, c.seg, pairs, Wr(L.B), Wr(L.eps), F, Wr(L.Wat));
+        if (c.Ns > 0)
+            NEP_LAUNCH("structure", (k_structure<R>), dim3(c.Ns), dim3(kRedBlock), 0, st, c.Ns, c.Na, c.atom_offset,
+                       Wr(L.Eat), Wr(L.Wat), F, loss ? 1 : 0, c.Et, static_cast<const R*>(c.Ft), c.Wt, c.has_v,
+                       c.lam_e, c.lam_f, c.lam_v, Es, Ws, Wd(L.ebar), Wd(L.Ubar), Wr(L.ubar), Wd(L.lossp));
+        if (!loss) return NEP_OK;
+    } else {
+        const long n = 9L * c.Ns > 3L * c.Na ? 9L * c.Ns : 3L * c.Na;
+        if (n > 0)
+            NEP_LAUNCH("seeds", (k_seeds<R>), dim3(int((n + kRedBlock - 1) / kRedBlock)), dim3(kRedBlock), 0, st,
+                       c.Ns, c.Na, c.dE, static_cast<const R*>(c.dF), c.dW, Wd(L.ebar), Wd(L.Ubar), Wr(L.ubar));
+    }
+
+    if (Na > 0) {
+        NEP_LAUNCH("tangent", (k_tangent<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types,
+                   c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dq), Wr(L.dA),
+                   Wr(L.S1));
+        NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(atom_grid), dim3(kBlock), 0, st, dm, theta,
+                   qscale, c.types, c.atom_struct, Na, Wd(L.ebar), q, Wr(L.dq), Wr(L.e), Wr(L.t), Wr(L.A), Wr(L.dA),
+                   Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.Bp));
+        const size_t shm = sizeof(R) * size_t(dm.T) * dm.T * Sh::NA * Sh::KA;
+        NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad<R, Sh, S>), dim3(L.ang_rows), dim3(kBlock), shm, st,
+                   dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.Bp), Wr(L.B),
+                   Wd(L.ang_part));
+        NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), 0, st, dm, qscale, c.types,
+                   c.species_order, Na, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha), Wr(L.beta),
+                   Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));
+    }
+    const int pgrid = int((dm.P + kRedBlock - 1) / kRedBlock);
+    NEP_LAUNCH("final_reduce", (k_final_reduce<R>), dim3(pgrid), dim3(kRedBlock), 0, st, dm, c.Ns, c.atom_offset,
+               Wd(L.outer_part), Na > 0 ? L.outer_rows : 0, Wd(L.ang_part), Na > 0 ? L.ang_rows : 0, Wd(L.ebar),
+               Wd(L.lossp), c.lam_e, c.lam_f, c.lam_v, static_cast<R*>(c.grad), loss ? c.loss : nullptr);
+    return NEP_OK;
+}
+
+}  // namespace nep
+
+// Instantiates both precisions of one shape and registers them.
+#define NEP_SHAPE_TU(KR, KA, NR, NA, L, H4, H5)                                                       \
+    namespace nep {                                                                                   \
+    nep_status shape_f32_##KR##_##KA##_##NR##_##NA##_##L##_##H4##_##H5(const Ctx& c) {                \
+        return run_shape<float, Shape<KR, KA, NR, NA, L, H4, H5>>(c);                                 \
+    }                                                                                                 \
+    nep_status shape_f64_##KR##_##KA##_##NR##_##NA##_##L##_##H4##_##H5(const Ctx& c) {                \
+        return run_shape<double, Shape<KR, KA, NR, NA, L, H4, H5>>(c);                                \
+    }                                                                                                 \
+    }

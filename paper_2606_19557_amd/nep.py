@@ -1,0 +1,374 @@
+"""Thin ctypes binding of libnep (``include/nep.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. PyTorch supplies device memory (tensors) and the current stream.
+The functions named ``nep_*`` mirror the C entry points one to one; the
+classes hold the device tensors the C structs point to.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnep.so")
+
+NEP_OK, NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED, NEP_ERR_CAPACITY, NEP_ERR_WORKSPACE, NEP_ERR_HIP = 0, -1, -2, -3, -4, -5
+NEP_F32, NEP_F64 = 0, 1
+
+EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_forward", "nep_loss_and_grad",
+           "nep_backward", "nep_adam_step", "nep_descriptor_scale", "nep_last_error", "nep_profile_enable",
+           "nep_profile_read")
+
+
+class NepError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libnep error {code}: {msg}")
+        self.code = code
+
+
+class c_model(C.Structure):
+    _fields_ = [("num_types", C.c_int32), ("n_max_r", C.c_int32), ("n_max_a", C.c_int32),
+                ("basis_r", C.c_int32), ("basis_a", C.c_int32), ("l_max", C.c_int32),
+                ("l_max_4b", C.c_int32), ("l_max_5b", C.c_int32), ("hidden", C.c_int32),
+                ("dtype", C.c_int32), ("rc_r", C.c_double), ("rc_a", C.c_double)]
+
+
+class c_batch(C.Structure):
+    _fields_ = [("num_structures", C.c_int32), ("num_atoms", C.c_int64), ("atom_offset", C.c_void_p),
+                ("positions", C.c_void_p), ("types", C.c_void_p), ("cells", C.c_void_p)]
+
+
+class c_neighbors(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("row_offset", C.c_void_p), ("seg_count", C.c_void_p),
+                ("pairs", C.c_void_p), ("atom_struct", C.c_void_p), ("species_order", C.c_void_p),
+                ("species_offset", C.c_void_p), ("num_pairs", C.c_int64), ("num_angular_pairs", C.c_int64)]
+
+
+class c_targets(C.Structure):
+    _fields_ = [("energy", C.c_void_p), ("force", C.c_void_p), ("virial", C.c_void_p),
+                ("has_virial", C.c_void_p), ("lambda_e", C.c_double), ("lambda_f", C.c_double),
+                ("lambda_v", C.c_double)]
+
+
+class c_adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("amsgrad", C.c_int32), ("amsgrad_mode", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnep.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2606_19557_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.nep_param_count.argtypes = [C.POINTER(c_model), C.POINTER(i64), C.POINTER(i64)]
+        L.nep_workspace_size.argtypes = [C.POINTER(c_model), i32, i64, i64, C.POINTER(C.c_size_t)]
+        L.nep_build_neighbors.argtypes = [C.POINTER(c_model), C.POINTER(c_batch), C.POINTER(c_neighbors), vp,
+                                          C.c_size_t, vp]
+        L.nep_forward.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors), vp, vp,
+                                  vp, vp, vp, C.c_size_t, vp]
+        L.nep_loss_and_grad.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
+                                        C.POINTER(c_targets), vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.nep_backward.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors), vp, vp,
+                                   vp, vp, vp, C.c_size_t, vp]
+        L.nep_adam_step.argtypes = [i64, i32, vp, vp, vp, vp, vp, i64, C.POINTER(c_adam), vp]
+        L.nep_descriptor_scale.argtypes = [i64, i64, i32, vp, vp, vp]
+        L.nep_last_error.restype = C.c_char_p
+        L.nep_profile_enable.argtypes = [i32]
+        L.nep_profile_read.argtypes = [i32, vp, vp, vp, C.POINTER(i32)]
+        for name in EXPORTS:
+            getattr(L, name).restype = C.c_char_p if name == "nep_last_error" else i32
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != NEP_OK:
+        raise NepError(code, lib().nep_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ model
+
+
+@dataclass(frozen=True)
+class Model:
+    num_types: int
+    rc_r: float
+    rc_a: float
+    n_max_r: int
+    n_max_a: int
+    basis_r: int
+    basis_a: int
+    l_max: int = 4
+    l_max_4b: int = 0
+    l_max_5b: int = 0
+    hidden: int = 30
+    dtype: str = "f32"
+
+    @property
+    def torch_dtype(self):
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def c(self) -> c_model:
+        return c_model(self.num_types, self.n_max_r, self.n_max_a, self.basis_r, self.basis_a, self.l_max,
+                       self.l_max_4b, self.l_max_5b, self.hidden, NEP_F64 if self.dtype == "f64" else NEP_F32,
+                       float(self.rc_r), float(self.rc_a))
+
+    @classmethod
+    def from_dict(cls, d: dict, dtype: str = "f32") -> "Model":
+        keys = ("num_types", "rc_r", "rc_a", "n_max_r", "n_max_a", "basis_r", "basis_a", "l_max", "l_max_4b",
+                "l_max_5b", "hidden")
+        return cls(**{k: d[k] for k in keys}, dtype=dtype)
+
+
+def nep_param_count(model: Model):
+    P, D = C.c_int64(), C.c_int64()
+    m = model.c()
+    _check(lib().nep_param_count(C.byref(m), C.byref(P), C.byref(D)))
+    return int(P.value), int(D.value)
+
+
+# ----------------------------------------------------------------- batch
+
+
+class Batch:
+    """Device-resident packed batch (positions in the model dtype)."""
+
+    def __init__(self, positions, types, cells, atom_offset, dtype=torch.float32, device="cuda"):
+        self.positions = torch.as_tensor(positions).to(device=device, dtype=dtype).contiguous()
+        self.types = torch.as_tensor(types).to(device=device, dtype=torch.int32).contiguous()
+        self.cells = torch.as_tensor(cells).to(device=device, dtype=torch.float64).reshape(-1, 3, 3).contiguous()
+        self.atom_offset = torch.as_tensor(atom_offset).to(device=device, dtype=torch.int64).contiguous()
+        self.num_structures = int(self.cells.shape[0])
+        self.num_atoms = int(self.positions.shape[0])
+        self.counts = torch.diff(self.atom_offset.cpu())
+
+    @classmethod
+    def from_host(cls, b, dtype=torch.float32, device="cuda"):
+        return cls(b.positions, b.types, b.cells, b.atom_offset, dtype=dtype, device=device)
+
+    def c(self) -> c_batch:
+        return c_batch(self.num_structures, self.num_atoms, _ptr(self.atom_offset), _ptr(self.positions),
+                       _ptr(self.types), _ptr(self.cells))
+
+
+class Neighbors:
+    """Device-resident neighbour lists (see nep_neighbors in nep.h)."""
+
+    def __init__(self, model: Model, batch: Batch, capacity: int):
+        dev = batch.positions.device
+        Na, T = batch.num_atoms, model.num_types
+        self.row_offset = torch.zeros(Na + 1, dtype=torch.int64, device=dev)
+        self.seg_count = torch.zeros((Na, T, 2), dtype=torch.int32, device=dev)
+        self.pairs = torch.zeros((max(capacity, 1), 4), dtype=model.torch_dtype, device=dev)
+        self.atom_struct = torch.zeros(max(Na, 1), dtype=torch.int32, device=dev)
+        self.species_order = torch.zeros(max(Na, 1), dtype=torch.int32, device=dev)
+        self.species_offset = torch.zeros(T + 1, dtype=torch.int64, device=dev)
+        self.capacity = capacity
+        self.num_pairs = -1
+        self.num_angular_pairs = -1
+
+    def c(self) -> c_neighbors:
+        return c_neighbors(self.capacity, _ptr(self.row_offset), _ptr(self.seg_count), _ptr(self.pairs),
+                           _ptr(self.atom_struct), _ptr(self.species_order), _ptr(self.species_offset),
+                           self.num_pairs, self.num_angular_pairs)
+
+    def neighbor_index(self):
+        """j of every pair (host int64), decoded from the 4th slot."""
+        w = self.pairs[: self.num_pairs, 3].contiguous()
+        if w.dtype == torch.float32:
+            return w.view(torch.int32).to(torch.int64).cpu()
+        return w.view(torch.int64).cpu()
+
+
+def nep_workspace_size(model: Model, num_structures: int, num_atoms: int, num_pairs: int) -> int:
+    n = C.c_size_t()
+    m = model.c()
+    _check(lib().nep_workspace_size(C.byref(m), int(num_structures), int(num_atoms), int(num_pairs), C.byref(n)))
+    return int(n.value)
+
+
+def workspace(model: Model, batch: Batch, nbr: Neighbors | None = None):
+    pairs = nbr.num_pairs if nbr is not None and nbr.num_pairs > 0 else 0
+    n = nep_workspace_size(model, batch.num_structures, batch.num_atoms, pairs)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=batch.positions.device)
+
+
+def nep_build_neighbors(model: Model, batch: Batch, capacity: int | None = None, ws=None) -> Neighbors:
+    """Build the lists; grows the pair buffer once when the first guess is short."""
+    if capacity is None:
+        capacity = max(1024, batch.num_atoms * 64)
+    ws = ws if ws is not None else workspace(model, batch)
+    for _ in range(2):
+        nb = Neighbors(model, batch, capacity)
+        m, b, cn = model.c(), batch.c(), nb.c()
+        code = lib().nep_build_neighbors(C.byref(m), C.byref(b), C.byref(cn), _ptr(ws), ws.numel(), _stream())
+        nb.num_pairs, nb.num_angular_pairs = int(cn.num_pairs), int(cn.num_angular_pairs)
+        if code == NEP_ERR_CAPACITY:
+            capacity = nb.num_pairs
+            continue
+        _check(code)
+        return nb
+    raise NepError(NEP_ERR_CAPACITY, "neighbour capacity retry failed")
+
+
+# --------------------------------------------------------------- compute
+
+
+def nep_forward(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, ws=None, want_force=True,
+                want_virial=True, want_descriptor=False):
+    """E [Ns] f64, F [Na,3], W [Ns,9] f64 (None when not asked) and optionally q [Na,D]."""
+    dev, dt = batch.positions.device, model.torch_dtype
+    P, D = nep_param_count(model)
+    ws = ws if ws is not None else workspace(model, batch, nbr)
+    E = torch.empty(batch.num_structures, dtype=torch.float64, device=dev)
+    F = torch.empty((batch.num_atoms, 3), dtype=dt, device=dev) if want_force else None
+    W = torch.empty((batch.num_structures, 9), dtype=torch.float64, device=dev) if want_virial else None
+    q = torch.empty((batch.num_atoms, D), dtype=dt, device=dev) if want_descriptor else None
+    m, b, cn = model.c(), batch.c(), nbr.c()
+    _check(lib().nep_forward(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), _ptr(E), _ptr(F),
+                             _ptr(W), _ptr(q), _ptr(ws), ws.numel(), _stream()))
+    return (E, F, W, q) if want_descriptor else (E, F, W)
+
+
+def nep_descriptors(model: Model, theta, batch: Batch, nbr: Neighbors, ws=None):
+    dev, dt = batch.positions.device, model.torch_dtype
+    _, D = nep_param_count(model)
+    ws = ws if ws is not None else workspace(model, batch, nbr)
+    q = torch.empty((batch.num_atoms, D), dtype=dt, device=dev)
+    m, b, cn = model.c(), batch.c(), nbr.c()
+    _check(lib().nep_forward(C.byref(m), _ptr(theta), None, C.byref(b), C.byref(cn), None, None, None, _ptr(q),
+                             _ptr(ws), ws.numel(), _stream()))
+    return q
+
+
+def nep_descriptor_scale(q):
+    s = torch.empty(q.shape[1], dtype=q.dtype, device=q.device)
+    _check(lib().nep_descriptor_scale(q.shape[0], q.shape[1], NEP_F64 if q.dtype == torch.float64 else NEP_F32,
+                                      _ptr(q), _ptr(s), _stream()))
+    return s
+
+
+class Targets:
+    def __init__(self, energy, force, virial, has_virial=None, lambdas=(1.0, 1.0, 0.1), dtype=torch.float32,
+                 device="cuda"):
+        self.energy = torch.as_tensor(energy).to(device=device, dtype=torch.float64).contiguous()
+        self.force = torch.as_tensor(force).to(device=device, dtype=dtype).reshape(-1, 3).contiguous()
+        self.virial = torch.as_tensor(virial).to(device=device, dtype=torch.float64).reshape(-1, 9).contiguous()
+        self.has_virial = None if has_virial is None else \
+            torch.as_tensor(has_virial).to(device=device, dtype=torch.uint8).contiguous()
+        self.lambdas = tuple(float(x) for x in lambdas)
+
+    def c(self) -> c_targets:
+        return c_targets(_ptr(self.energy), _ptr(self.force), _ptr(self.virial), _ptr(self.has_virial),
+                         *self.lambdas)
+
+
+def nep_loss_and_grad(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, targets: Targets, ws=None,
+                      grad=None, loss=None, want_predictions=False):
+    """Returns (loss[4] f64 device, grad [P]) and, when asked, (E, F, W)."""
+    dev, dt = batch.positions.device, model.torch_dtype
+    P, _ = nep_param_count(model)
+    ws = ws if ws is not None else workspace(model, batch, nbr)
+    grad = grad if grad is not None else torch.empty(P, dtype=dt, device=dev)
+    loss = loss if loss is not None else torch.empty(4, dtype=torch.float64, device=dev)
+    E = F = W = None
+    if want_predictions:
+        E = torch.empty(batch.num_structures, dtype=torch.float64, device=dev)
+        F = torch.empty((batch.num_atoms, 3), dtype=dt, device=dev)
+        W = torch.empty((batch.num_structures, 9), dtype=torch.float64, device=dev)
+    m, b, cn, tg = model.c(), batch.c(), nbr.c(), targets.c()
+    _check(lib().nep_loss_and_grad(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), C.byref(tg),
+                                   _ptr(loss), _ptr(grad), _ptr(E), _ptr(F), _ptr(W), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return (loss, grad, E, F, W) if want_predictions else (loss, grad)
+
+
+def nep_backward(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, dE=None, dF=None, dW=None, ws=None):
+    dev, dt = batch.positions.device, model.torch_dtype
+    P, _ = nep_param_count(model)
+    ws = ws if ws is not None else workspace(model, batch, nbr)
+    grad = torch.empty(P, dtype=dt, device=dev)
+    dE = None if dE is None else dE.to(dtype=torch.float64).contiguous()
+    dF = None if dF is None else dF.to(dtype=dt).contiguous()
+    dW = None if dW is None else dW.to(dtype=torch.float64).reshape(-1, 9).contiguous()
+    m, b, cn = model.c(), batch.c(), nbr.c()
+    _check(lib().nep_backward(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), _ptr(dE), _ptr(dF),
+                              _ptr(dW), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
+    return grad
+
+
+@dataclass
+class AdamConfig:
+    lr: float = 5e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    amsgrad: bool = True
+    mode: str = "paper"  # "paper" (max of bias-corrected v, Eq. 12) or "torch"
+
+    def c(self) -> c_adam:
+        return c_adam(self.lr, self.beta1, self.beta2, self.eps, 1 if self.amsgrad else 0,
+                      0 if self.mode == "paper" else 1)
+
+
+def nep_adam_step(theta, grad, m, v, vmax, t: int, cfg: AdamConfig):
+    dt = NEP_F64 if theta.dtype == torch.float64 else NEP_F32
+    c = cfg.c()
+    _check(lib().nep_adam_step(theta.numel(), dt, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), _ptr(vmax), int(t),
+                               C.byref(c), _stream()))
+
+
+def nep_profile_enable(on: bool):
+    _check(lib().nep_profile_enable(1 if on else 0))
+
+
+def nep_profile_read(cap: int = 64):
+    names = (C.c_char * 64 * cap)()
+    launches = (C.c_int64 * cap)()
+    total = (C.c_double * cap)()
+    count = C.c_int32()
+    _check(lib().nep_profile_read(cap, C.cast(names, C.c_void_p), C.cast(launches, C.c_void_p),
+                                  C.cast(total, C.c_void_p), C.byref(count)))
+    return {bytes(names[k]).split(b"\0")[0].decode(): (int(launches[k]), float(total[k]))
+            for k in range(min(cap, count.value))}
+
+
+# ------------------------------------------------------- autograd function
+
+
+class NEPFunction(torch.autograd.Function):
+    """theta -> (E, F, W) with a hand-written backward (nep_backward, a VJP
+    whose force and virial parts are the mixed second derivative d^2E/dtheta dr)."""
+
+    @staticmethod
+    def forward(ctx, theta, model, q_scale, batch, nbr, ws):
+        E, F, W = nep_forward(model, theta.detach(), q_scale, batch, nbr, ws)
+        ctx.save_for_backward(theta)
+        ctx.meta = (model, q_scale, batch, nbr, ws)
+        return E, F, W
+
+    @staticmethod
+    def backward(ctx, dE, dF, dW):
+        (theta,) = ctx.saved_tensors
+        model, q_scale, batch, nbr, ws = ctx.meta
+        g = nep_backward(model, theta.detach(), q_scale, batch, nbr, dE, dF, dW, ws)
+        return g, None, None, None, None, None

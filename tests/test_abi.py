@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every declared entry point, and its host-side
+logic (parameter layout, workspace sizes, argument validation) works without a GPU."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nep.h")
+
+nep = pytest.importorskip("paper_2606_19557_amd.nep")
+
+
+def _lib_or_skip():
+    if not os.path.exists(nep.LIB_PATH):
+        pytest.skip("libnep.so not built (run __graft_entry__.build())")
+    return nep.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:nep_status|const char\*)\s+(nep_\w+)\(", text, re.M)))
+
+
+def test_header_declares_required_calls():
+    syms = declared_symbols()
+    for name in ("nep_build_neighbors", "nep_forward", "nep_loss_and_grad", "nep_adam_step"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    assert set(declared_symbols()) == set(nep.EXPORTS)
+
+
+def test_param_count_matches_table2():
+    """The library's parameter layout reproduces Table II's trainable-parameter counts."""
+    _lib_or_skip()
+    import json
+
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_param_counts.json")))
+    for case in g["cases"]:
+        m = nep.Model(num_types=g["num_types"], rc_r=5.0, rc_a=4.0, n_max_r=case["n_max"][0],
+                      n_max_a=case["n_max"][1], basis_r=8, basis_a=8, l_max=4, l_max_4b=2, l_max_5b=1,
+                      hidden=g["hidden"])
+        assert nep.nep_param_count(m)[0] == case["params"]
+
+
+def test_param_count_matches_oracle():
+    _lib_or_skip()
+    import oracle as O
+    from synth import WORKLOADS
+
+    for w in WORKLOADS.values():
+        assert nep.nep_param_count(nep.Model.from_dict(w.model))[:2] == O.dims(O.Model(**w.model))
+
+
+def test_invalid_models_rejected():
+    _lib_or_skip()
+    base = dict(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30)
+    bad = [dict(rc_a=7.0), dict(l_max_4b=3), dict(l_max=5), dict(num_types=0), dict(num_types=17), dict(hidden=0)]
+    for b in bad:
+        with pytest.raises(nep.NepError) as e:
+            nep.nep_param_count(nep.Model(**{**base, **b}))
+        assert e.value.code in (nep.NEP_ERR_INVALID_ARG, nep.NEP_ERR_UNSUPPORTED)
+
+
+def test_workspace_size_grows_with_atoms():
+    _lib_or_skip()
+    m = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30)
+    a = nep.nep_workspace_size(m, 10, 1000, 50000)
+    b = nep.nep_workspace_size(m, 10, 2000, 100000)
+    assert 0 < a < b
+    with pytest.raises(nep.NepError):
+        nep.nep_workspace_size(m, -1, 10, 10)
+
+
+def test_calls_validate_before_launching():
+    """NULL arguments and unsupported shapes fail on the host with an error code and message."""
+    L = _lib_or_skip()
+    m = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30).c()
+    rc = L.nep_forward(C.byref(m), None, None, None, None, None, None, None, None, None, 0, None)
+    assert rc == nep.NEP_ERR_INVALID_ARG and L.nep_last_error()
+    batch = nep.c_batch(1, 4, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8))
+    nb = nep.c_neighbors(0, *([C.c_void_p(8)] * 6), 0, 0)
+    odd = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=5, n_max_a=4, basis_r=8, basis_a=8, hidden=30).c()
+    rc = L.nep_forward(C.byref(odd), C.c_void_p(8), C.c_void_p(8), C.byref(batch), C.byref(nb), C.c_void_p(8),
+                       None, None, None, C.c_void_p(8), 1 << 20, None)
+    assert rc == nep.NEP_ERR_UNSUPPORTED and b"no compiled kernel" in L.nep_last_error()
+    cfg = nep.AdamConfig().c()
+    assert L.nep_adam_step(10, 0, None, None, None, None, None, 0, C.byref(cfg), None) == nep.NEP_ERR_INVALID_ARG
+    assert L.nep_adam_step(0, 0, None, None, None, None, None, 1, C.byref(cfg), None) == nep.NEP_OK
