@@ -202,13 +202,13 @@ static nep_status check_batch(const nep_batch* b) {
 
 static nep_status check_nbr(const nep_neighbors* n, const nep_batch* b) {
     if (!n) return fail(NEP_ERR_INVALID_ARG, "neighbors is NULL");
-    if (!n->row_offset || !n->seg_count || !n->atom_struct || !n->species_order || !n->species_offset)
+    if (!n->row_offset || !n->species_offset ||
+        (b->num_atoms > 0 && (!n->seg_count || !n->atom_struct || !n->species_order)))
         return fail(NEP_ERR_INVALID_ARG, "a neighbour array is NULL");
     if (n->num_pairs < 0 || n->num_pairs > n->capacity)
         return fail(NEP_ERR_INVALID_ARG, "neighbour list not built (num_pairs %lld, capacity %lld)",
                     (long long)n->num_pairs, (long long)n->capacity);
     if (n->num_pairs > 0 && !n->pairs) return fail(NEP_ERR_INVALID_ARG, "pairs is NULL");
-    (void)b;
     return NEP_OK;
 }
 
@@ -230,7 +230,8 @@ static nep_status base_ctx(const nep_model* model, const void* theta, const void
                     model->n_max_r, model->n_max_a, model->basis_r, model->basis_a, model->l_max, model->l_max_4b,
                     model->l_max_5b);
     c->f64 = model->dtype == NEP_F64;
-    const size_t shm = (c->f64 ? 8 : 4) * size_t(c->dm.T) * c->dm.T * c->dm.NA * c->dm.KA;
+    const size_t shm = (c->f64 ? 8 : 4) * (size_t(c->dm.T) * c->dm.T + kBlock / kTeam) * c->dm.NA * c->dm.KA +
+                       sizeof(int) * (kBlock / kTeam);
     if (shm > 64 * 1024) return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block too large for LDS (%zu bytes)", shm);
     c->stream = static_cast<hipStream_t>(stream);
     c->mode = mode;
@@ -293,8 +294,8 @@ nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, n
     nep_status s;
     if ((s = make_dims(model, &c.dm))) return s;
     if ((s = check_batch(batch))) return s;
-    if (!nbr || !nbr->row_offset || !nbr->seg_count || !nbr->atom_struct || !nbr->species_order ||
-        !nbr->species_offset)
+    if (!nbr || !nbr->row_offset || !nbr->species_offset ||
+        (batch->num_atoms > 0 && (!nbr->seg_count || !nbr->atom_struct || !nbr->species_order)))
         return fail(NEP_ERR_INVALID_ARG, "a neighbour array is NULL");
     if (nbr->capacity < 0 || (nbr->capacity > 0 && !nbr->pairs))
         return fail(NEP_ERR_INVALID_ARG, "bad pair capacity or buffer");

@@ -546,6 +546,8 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
 // dL/dc_A[a][b][n][k] = sum_{i in a} sum_{j in b, angular}
 //     [ f_k (sum_lm Bp_nlm Y_lm + Q_nlm v.dY_lm) + f_k' (v.r^) sum_lm Q_nlm Y_lm ],
 // Q = B = dE_i/dA. Per-block partial rows (double) over a grid-stride loop.
+// Each team's per-segment sums go to its own LDS slot and are then added into
+// the block accumulator in team order, so the result is bitwise repeatable.
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
 k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
@@ -553,10 +555,13 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
                      const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ Bp_in,
                      const R* __restrict__ Q_in, double* __restrict__ partial) {
     constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM;
+    constexpr int NK = NA * KA, TEAMS = kBlock / S;
     extern __shared__ unsigned char smem_raw[];
     R* G = reinterpret_cast<R*>(smem_raw);
     const int T = dm.T;
-    const int G_len = T * T * NA * KA;
+    const int G_len = T * T * NK;
+    R* slot = G + G_len;                   // [TEAMS][NK]
+    int* team_type = reinterpret_cast<int*>(slot + TEAMS * NK);  // [TEAMS]
     for (int x = threadIdx.x; x < G_len; x += kBlock) G[x] = R(0);
     __syncthreads();
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
@@ -626,8 +631,13 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
 #pragma unroll
                 for (int kk = 0; kk < KA; ++kk) {
                     const R vsum = team_sum<S>(acc[n][kk]);
-                    if (live && (n * KA + kk) % S == lane) atomicAdd(&G[((a * T + b) * NA + n) * KA + kk], vsum);
+                    if ((n * KA + kk) % S == lane) slot[team * NK + n * KA + kk] = live ? vsum : R(0);
                 }
+            if (lane == 0) team_type[team] = a;
+            __syncthreads();
+            for (int x = threadIdx.x; x < NK; x += kBlock)
+                for (int tm = 0; tm < TEAMS; ++tm) G[(team_type[tm] * T + b) * NK + x] += slot[tm * NK + x];
+            __syncthreads();
         }
     }
     __syncthreads();

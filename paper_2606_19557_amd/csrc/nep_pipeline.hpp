@@ -67,7 +67,7 @@ nep_status run_shape(const Ctx& c) {
         NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(atom_grid), dim3(kBlock), 0, st, dm, theta,
                    qscale, c.types, c.atom_struct, Na, Wd(L.ebar), q, Wr(L.dq), Wr(L.e), Wr(L.t), Wr(L.A), Wr(L.dA),
                    Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.Bp));
-        const size_t shm = sizeof(R) * size_t(dm.T) * dm.T * Sh::NA * Sh::KA;
+        const size_t shm = sizeof(R) * (size_t(dm.T) * dm.T + kBlock / S) * Sh::NA * Sh::KA + sizeof(int) * (kBlock / S);
         NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad<R, Sh, S>), dim3(L.ang_rows), dim3(kBlock), shm, st,
                    dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.Bp), Wr(L.B),
                    Wd(L.ang_part));
