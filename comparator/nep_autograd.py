@@ -95,6 +95,24 @@ class AutogradNEP:
         ti, tj = self.types[self.pi], self.types[self.pj]
         self.tpair = ti * T + tj
         self.tpair_a = self.tpair[self.ang]
+        self.tpair_groups = self._groups(self.tpair)
+        self.tpair_a_groups = self._groups(self.tpair_a)
+
+    def _groups(self, tp):
+        """Pair indices of each species pair present (None when there is one species)."""
+        if self.T == 1:
+            return None
+        return [(int(ab), torch.nonzero(tp == ab).flatten()) for ab in torch.unique(tp).tolist()]
+
+    @staticmethod
+    def _expand(f, c, groups):
+        """g[p, n] = sum_k c[ab(p), n, k] f[p, k], one matmul per species pair."""
+        if groups is None:
+            return f @ c[0].T
+        g = torch.zeros(f.shape[0], c.shape[1], dtype=f.dtype, device=f.device)
+        for ab, idx in groups:
+            g = g.index_put((idx,), f[idx] @ c[ab].T)
+        return g
 
     # -------------------------------------------------------------- pieces
 
@@ -104,13 +122,13 @@ class AutogradNEP:
         cA = theta[self.offA: self.offN].reshape(T * T, NA, KA)
         d = r.norm(dim=1)
         fR = _chebyshev(d, self.m["rc_r"], KR)  # [p, KR]
-        gR = torch.einsum("pk,pnk->pn", fR, cR[self.tpair])
+        gR = self._expand(fR, cR, self.tpair_groups)
         q_rad = torch.zeros(self.Na, NR, dtype=r.dtype, device=r.device).index_add(0, self.pi, gR)
         ra = r[self.ang]
         da = d[self.ang]
         u = ra / da[:, None]
         fA = _chebyshev(da, self.m["rc_a"], KA)
-        gA = torch.einsum("pk,pnk->pn", fA, cA[self.tpair_a])  # [pa, NA]
+        gA = self._expand(fA, cA, self.tpair_a_groups)  # [pa, NA]
         Y = _real_harmonics(u, L)  # [pa, LM]
         A = torch.zeros(self.Na, NA, Y.shape[1], dtype=r.dtype, device=r.device)
         A = A.index_add(0, self.pi[self.ang], gA[:, :, None] * Y[:, None, :])

@@ -100,10 +100,12 @@ typedef struct {
     int32_t* seg_count;       /* [Na][T][2]: {pairs, angular pairs} per neighbour species */
     void* pairs;              /* [capacity][4] dtype: r_ij x, y, z and the neighbour index j
                                  stored bit-for-bit in the 4th slot (int32 in float, int64 in double) */
+    int32_t* reverse;         /* [capacity] index of the reverse pair (j, i, -n) of each pair, -1 if absent */
     int32_t* atom_struct;     /* [Na] structure index of each atom */
     int32_t* species_order;   /* [Na] atoms sorted by species (stable) */
     int64_t* species_offset;  /* [T+1] start of each species in species_order */
-    int64_t num_pairs;        /* host, written by nep_build_neighbors (also on NEP_ERR_CAPACITY) */
+    int64_t num_pairs;        /* host, written by nep_build_neighbors (also on NEP_ERR_CAPACITY);
+                                 at most 2^31 - 1 pairs per batch */
     int64_t num_angular_pairs;/* host, written by nep_build_neighbors */
 } nep_neighbors;
 

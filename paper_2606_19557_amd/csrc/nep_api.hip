@@ -105,7 +105,7 @@ const ShapeEntry* find_shape(const Dims& d) {
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(const Dims& dm, bool f64, int Ns, long Na) {
+Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs) {
     Layout L{};
     const size_t r = f64 ? 8 : 4;
     const size_t na = size_t(Na > 0 ? Na : 0), ns = size_t(Ns > 0 ? Ns : 0);
@@ -126,6 +126,8 @@ Layout make_layout(const Dims& dm, bool f64, int Ns, long Na) {
     L.B = take(r * na * dm.NA * dm.LM);
     L.eps = take(r * na * dm.T * dm.KR);
     L.F = take(r * na * 3);
+    L.Fown = take(r * na * 3);
+    L.h = take(4 * r * size_t(pairs > 0 ? pairs : 0));
     L.Wat = take(r * na * 9);
     L.ubar = take(r * na * 3);
     L.dq = take(r * na * dm.D);
@@ -143,13 +145,14 @@ Layout make_layout(const Dims& dm, bool f64, int Ns, long Na) {
     const long tiles = (Na + kBlock / kTeam - 1) / (kBlock / kTeam);
     L.ang_rows = int(tiles < kMaxAngRows ? tiles : kMaxAngRows);
     if (L.ang_rows < 1) L.ang_rows = 1;
+    // outer reduction: one species-tagged row per chunk of kOuterChunk atoms of
+    // one species; at most ceil(Na / chunk) + T chunks.
     L.outer_chunk = kOuterChunk;
-    const long chunks = (Na + kOuterChunk - 1) / kOuterChunk;
-    L.outer_rows = int(chunks < kMaxOuterRows ? chunks : kMaxOuterRows);
-    if (L.outer_rows < 1) L.outer_rows = 1;
-    const size_t rowlen = size_t(dm.offA) + size_t(dm.offB1 - dm.offN);
-    L.outer_part = take(8 * rowlen * size_t(L.outer_rows));
+    L.outer_rows = int((Na + kOuterChunk - 1) / kOuterChunk) + dm.T;
+    const size_t W1 = size_t(dm.D + 2) * dm.H + size_t(dm.T) * dm.NR * dm.KR;
+    L.outer_part = take(8 * (W1 + 1) * size_t(L.outer_rows));
     L.ang_part = take(8 * size_t(dm.offN - dm.offA) * size_t(L.ang_rows));
+    L.stage = take(8 * size_t(dm.offB1) * size_t(kStageGroups));
     L.total = o;
     return L;
 }
@@ -208,7 +211,7 @@ static nep_status check_nbr(const nep_neighbors* n, const nep_batch* b) {
     if (n->num_pairs < 0 || n->num_pairs > n->capacity)
         return fail(NEP_ERR_INVALID_ARG, "neighbour list not built (num_pairs %lld, capacity %lld)",
                     (long long)n->num_pairs, (long long)n->capacity);
-    if (n->num_pairs > 0 && !n->pairs) return fail(NEP_ERR_INVALID_ARG, "pairs is NULL");
+    if (n->num_pairs > 0 && (!n->pairs || !n->reverse)) return fail(NEP_ERR_INVALID_ARG, "pairs or reverse is NULL");
     return NEP_OK;
 }
 
@@ -230,9 +233,15 @@ static nep_status base_ctx(const nep_model* model, const void* theta, const void
                     model->n_max_r, model->n_max_a, model->basis_r, model->basis_a, model->l_max, model->l_max_4b,
                     model->l_max_5b);
     c->f64 = model->dtype == NEP_F64;
-    const size_t shm = (c->f64 ? 8 : 4) * (size_t(c->dm.T) * c->dm.T + kBlock / kTeam) * c->dm.NA * c->dm.KA +
-                       sizeof(int) * (kBlock / kTeam);
-    if (shm > 64 * 1024) return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block too large for LDS (%zu bytes)", shm);
+    {
+        // LDS of the angular-coefficient gradient block: accumulator, team
+        // slots, the atoms' adjoints and the exchange buffers (<= 160 KB)
+        const size_t r = c->f64 ? 8 : 4, teams = kBlock / kTeam, nk = size_t(c->dm.NA) * c->dm.KA;
+        const size_t shm = r * (size_t(c->dm.T) * c->dm.T * nk + teams * nk + teams * 2 * c->dm.NA * c->dm.LM +
+                                teams * kTeam * (c->dm.NA + c->dm.KA + 1)) + sizeof(int) * teams;
+        if (shm > 160 * 1024)
+            return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block too large for LDS (%zu bytes)", shm);
+    }
     c->stream = static_cast<hipStream_t>(stream);
     c->mode = mode;
     c->Ns = batch->num_structures;
@@ -243,8 +252,10 @@ static nep_status base_ctx(const nep_model* model, const void* theta, const void
     c->row = nbr->row_offset;
     c->seg = nbr->seg_count;
     c->pair_data = nbr->pairs;
+    c->reverse = nbr->reverse;
     c->atom_struct = nbr->atom_struct;
     c->species_order = nbr->species_order;
+    c->species_offset = nbr->species_offset;
     c->theta = theta;
     c->qscale = q_scale;
     if (!ws) return fail(NEP_ERR_INVALID_ARG, "workspace is NULL");
@@ -282,7 +293,7 @@ nep_status nep_workspace_size(const nep_model* model, int32_t num_structures, in
     if (s) return s;
     if (!bytes || num_structures < 0 || num_atoms < 0 || num_pairs < 0)
         return fail(NEP_ERR_INVALID_ARG, "bad workspace query");
-    *bytes = make_layout(d, model->dtype == NEP_F64, num_structures, long(num_atoms)).total;
+    *bytes = make_layout(d, model->dtype == NEP_F64, num_structures, long(num_atoms), long(num_pairs)).total;
     return NEP_OK;
 }
 
@@ -297,7 +308,7 @@ nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, n
     if (!nbr || !nbr->row_offset || !nbr->species_offset ||
         (batch->num_atoms > 0 && (!nbr->seg_count || !nbr->atom_struct || !nbr->species_order)))
         return fail(NEP_ERR_INVALID_ARG, "a neighbour array is NULL");
-    if (nbr->capacity < 0 || (nbr->capacity > 0 && !nbr->pairs))
+    if (nbr->capacity < 0 || (nbr->capacity > 0 && (!nbr->pairs || !nbr->reverse)))
         return fail(NEP_ERR_INVALID_ARG, "bad pair capacity or buffer");
     if (!ws) return fail(NEP_ERR_INVALID_ARG, "workspace is NULL");
     c.f64 = model->dtype == NEP_F64;

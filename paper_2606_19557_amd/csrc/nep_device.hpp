@@ -270,4 +270,50 @@ __device__ __forceinline__ R team_sum(R v) {
     return v;
 }
 
+// --------------------------------------------------------- team exchange
+
+// Per-atom moment accumulation M[n][lm] += sum_pairs u_n(p) Y_lm(p) without
+// per-lane copies of all of M: the S lanes of a team each evaluate one pair,
+// publish (u, Y) in the team's LDS slots, and every lane then accumulates only
+// the harmonics it owns, lm = lane + S*o, over all S pairs of the batch.
+template <typename R, int NA, int LM, int S>
+struct MomentExchange {
+    static constexpr int OWN = (LM + S - 1) / S;
+    static constexpr int SLOT = NA + LM + 1;  // +1 spreads the lane slots over banks
+    static constexpr int TEAM_FLOATS = S * SLOT;
+
+    __device__ static void wave_fence() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // acc[n][o] += sum over the team's lanes q of u_q[n] * Y_q[lane + S*o]
+    __device__ static void accumulate(R* team_buf, int lane, const R* u, const R* Y, R (&acc)[NA][OWN]) {
+        R* mine = team_buf + lane * SLOT;
+#pragma unroll
+        for (int n = 0; n < NA; ++n) mine[n] = u[n];
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) mine[NA + lm] = Y[lm];
+        wave_fence();
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const R* src = team_buf + q * SLOT;
+            R yv[OWN];
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) {
+                const int lm = lane + S * o;
+                yv[o] = (lm < LM) ? src[NA + lm] : R(0);
+            }
+#pragma unroll
+            for (int n = 0; n < NA; ++n) {
+                const R un = src[n];
+#pragma unroll
+                for (int o = 0; o < OWN; ++o) acc[n][o] += un * yv[o];
+            }
+        }
+        wave_fence();
+    }
+};
+
 }  // namespace nep

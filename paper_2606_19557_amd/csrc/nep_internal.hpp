@@ -59,8 +59,10 @@ struct Ctx {
     const int64_t* row;
     const int* seg;
     const void* pair_data;
+    const int* reverse;
     const int* atom_struct;
     const int* species_order;
+    const int64_t* species_offset;
     // parameters
     const void* theta;
     const void* qscale;
@@ -87,19 +89,18 @@ struct Ctx {
 
 // Workspace carve-up (byte offsets), identical for every shape of given sizes.
 struct Layout {
-    size_t q, A, S0, S1, Eat, e, t, B, eps, F, Wat, ubar, dq, dA, abar, alpha, beta, gam, Bp;
-    size_t Es, Ws, ebar, Ubar, lossp, outer_part, ang_part, nbr_totals;
+    size_t q, A, S0, S1, Eat, e, t, B, eps, F, Fown, Wat, ubar, dq, dA, abar, alpha, beta, gam, Bp, h;
+    size_t Es, Ws, ebar, Ubar, lossp, outer_part, ang_part, stage, nbr_totals;
     size_t total;
     int outer_rows, ang_rows, outer_chunk;
 };
 
-Layout make_layout(const Dims& dm, bool f64, int Ns, long Na);
+Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs);
 
 // Team size (lanes per atom) of the pair sweeps and the grid caps.
 constexpr int kTeam = 8;
-constexpr int kMaxAngRows = 2048;
-constexpr int kMaxOuterRows = 1024;
-constexpr int kOuterChunk = 256;
+constexpr int kMaxAngRows = 512;
+constexpr int kOuterChunk = 64;
 
 // Per-shape pipeline (forward / loss+grad / backward / descriptors).
 using ShapeFn = nep_status (*)(const Ctx&);

@@ -26,27 +26,33 @@ __device__ __forceinline__ R load_theta(const R* __restrict__ th, long idx) {
 // q (radial, Eqs. 15-16; angular invariants, Eqs. 19-20 and the 4/5-body
 // contractions), the angular moments A[n][lm], and the per-neighbour-species
 // radial basis sums S0[b][k] = sum_{j in b} f_k(r_ij) used by the gradient.
+// Angular pairs are processed S at a time by the team and their (g_n, Y_lm)
+// exchanged through LDS; each lane owns the moments lm = lane + S*o.
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
 k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
              const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
              R* __restrict__ q_out, R* __restrict__ A_out, R* __restrict__ S0_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D;
+    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D, L = Sh::L;
+    using X = MomentExchange<R, NA, LM, S>;
+    constexpr int OWN = X::OWN, TEAMS = kBlock / S;
+    __shared__ R xbuf[TEAMS * X::TEAM_FLOATS];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = blockIdx.x * (kBlock / S) + team;
+    R* tbuf = xbuf + team * X::TEAM_FLOATS;
+    const int i = blockIdx.x * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
     const int a = live ? types[i] : 0;
     int64_t p = live ? row[i] : 0;
     R qR[NR];
-    R A[NA][LM];
 #pragma unroll
     for (int n = 0; n < NR; ++n) qR[n] = R(0);
+    R acc[NA][OWN];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
-        for (int lm = 0; lm < LM; ++lm) A[n][lm] = R(0);
+        for (int o = 0; o < OWN; ++o) acc[n][o] = R(0);
 
     for (int b = 0; b < T; ++b) {
         const int tot = live ? seg[(i * T + b) * 2] : 0;
@@ -55,29 +61,40 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
         R Sb[KR];
 #pragma unroll
         for (int k = 0; k < KR; ++k) Sb[k] = R(0);
-        for (int k = lane; k < tot; k += S) {
+        // angular pairs, one batch of S per iteration (team-uniform trip count)
+        for (int base = 0; base < ang; base += S) {
+            const int k = base + lane;
+            R g[NA], Y[LM];
+#pragma unroll
+            for (int n = 0; n < NA; ++n) g[n] = R(0);
+#pragma unroll
+            for (int lm = 0; lm < LM; ++lm) Y[lm] = R(0);
+            if (k < ang) {
+                const Rec<R> pr = pairs[p + k];
+                const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
+                R f[KR];
+                cheb_basis<R, KR, false>(r, rcR, irR, f, nullptr);
+#pragma unroll
+                for (int kk = 0; kk < KR; ++kk) Sb[kk] += f[kk];
+                R fa[KA];
+                cheb_basis<R, KA, false>(r, rcA, irA, fa, nullptr);
+                const R ir = R(1) / r;
+                solid_harmonics<R, R, L>(pr.x * ir, pr.y * ir, pr.z * ir, Y);
+#pragma unroll
+                for (int n = 0; n < NA; ++n)
+#pragma unroll
+                    for (int kk = 0; kk < KA; ++kk) g[n] += cA[n * KA + kk] * fa[kk];
+            }
+            X::accumulate(tbuf, lane, g, Y, acc);
+        }
+        // radial-only pairs
+        for (int k = ang + lane; k < tot; k += S) {
             const Rec<R> pr = pairs[p + k];
             const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
             R f[KR];
             cheb_basis<R, KR, false>(r, rcR, irR, f, nullptr);
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) Sb[kk] += f[kk];
-            if (k < ang) {
-                R fa[KA];
-                cheb_basis<R, KA, false>(r, rcA, irA, fa, nullptr);
-                const R ir = R(1) / r;
-                const R ux = pr.x * ir, uy = pr.y * ir, uz = pr.z * ir;
-                R Y[LM];
-                solid_harmonics<R, R, Sh::L>(ux, uy, uz, Y);
-#pragma unroll
-                for (int n = 0; n < NA; ++n) {
-                    R g = R(0);
-#pragma unroll
-                    for (int kk = 0; kk < KA; ++kk) g += cA[n * KA + kk] * fa[kk];
-#pragma unroll
-                    for (int lm = 0; lm < LM; ++lm) A[n][lm] += g * Y[lm];
-                }
-            }
         }
         p += tot;
 #pragma unroll
@@ -93,166 +110,106 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
                 if (kk % S == lane) S0_out[((long)i * T + b) * KR + kk] = Sb[kk];
         }
     }
+    // invariants: partial sums over owned harmonics, summed over the team
+    R qA[NA * L];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
-        for (int lm = 0; lm < LM; ++lm) A[n][lm] = team_sum<S>(A[n][lm]);
-
-    R q[D];
+        for (int l = 1; l <= L; ++l) {
+            R s2 = R(0);
 #pragma unroll
-    for (int n = 0; n < NR; ++n) q[n] = qR[n];
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-#pragma unroll
-        for (int l = 1; l <= Sh::L; ++l) {
-            R s = R(0);
-#pragma unroll
-            for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) s += A[n][lm] * A[n][lm];
-            q[NR + (l - 1) * NA + n] = s;
+            for (int o = 0; o < OWN; ++o) {
+                const int lm = lane + S * o;
+                if (lm < LM && lm_degree<LM>(lm) == l) s2 += acc[n][o] * acc[n][o];
+            }
+            qA[(l - 1) * NA + n] = team_sum<S>(s2);
         }
-        if (Sh::H4) q[NR + Sh::L * NA + n] = q4_value<R>(&A[n][3]);
-        if (Sh::H5) {
-            const R P = q[NR + n];
-            q[NR + (Sh::L + (Sh::H4 ? 1 : 0)) * NA + n] = P * P;
+    R q4v[NA];
+    if (Sh::H4) {
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            R a2[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) a2[m] = __shfl(acc[n][(3 + m) / S], (threadIdx.x & ~(S - 1)) + (3 + m) % S, 64);
+            q4v[n] = q4_value<R>(a2);
         }
     }
     if (live) {
 #pragma unroll
-        for (int d = 0; d < D; ++d)
-            if (d % S == lane) q_out[(long)i * D + d] = q[d];
+        for (int d = 0; d < D; ++d) {
+            if (d % S != lane) continue;
+            R v;
+            if (d < NR) {
+                v = qR[d];
+            } else if (d < NR + L * NA) {
+                v = qA[d - NR];
+            } else if (Sh::H4 && d < NR + (L + 1) * NA) {
+                v = q4v[d - NR - L * NA];
+            } else {
+                const R P = qA[d - NR - (L + (Sh::H4 ? 1 : 0)) * NA];  // l = 1 three-body term
+                v = P * P;
+            }
+            q_out[(long)i * D + d] = v;
+        }
 #pragma unroll
         for (int n = 0; n < NA; ++n)
 #pragma unroll
-            for (int lm = 0; lm < LM; ++lm)
-                if ((n * LM + lm) % S == lane) A_out[((long)i * NA + n) * LM + lm] = A[n][lm];
-    }
-}
-
-// -------------------------------------------------------------- network fwd
-
-// E_i, e = dE_i/dq (Eqs. 2-3), tanh activations, B = dE_i/dA[n][lm] and the
-// radial force coefficients eps[b][k] = sum_n e_n c_R[a][b][n][k].
-template <typename R, class Sh>
-__global__ void __launch_bounds__(kBlock)
-k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
-                  const int* __restrict__ types, int Na, const R* __restrict__ q_in, const R* __restrict__ A_in,
-                  R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out, R* __restrict__ B_out,
-                  R* __restrict__ eps_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, LM = Sh::LM, D = Sh::D;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Na) return;
-    const int T = dm.T, H = dm.H;
-    const int a = types[i];
-    R qs[D], e[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        qs[d] = q_in[(long)i * D + d] * qscale[d];
-        e[d] = R(0);
-    }
-    const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
-    const R* __restrict__ b0 = W0 + (long)H * D;
-    const R* __restrict__ w1 = b0 + H;
-    R E = -theta[dm.offB1];
-    for (int mu = 0; mu < H; ++mu) {
-        R acc = -b0[mu];
-#pragma unroll
-        for (int d = 0; d < D; ++d) acc += W0[(long)mu * D + d] * qs[d];
-        const R t = tanh_<R>(acc);
-        t_out[(long)i * H + mu] = t;
-        const R w = w1[mu];
-        E += w * t;
-        const R c = w * (R(1) - t * t);
-#pragma unroll
-        for (int d = 0; d < D; ++d) e[d] += c * W0[(long)mu * D + d];
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        e[d] *= qscale[d];
-        e_out[(long)i * D + d] = e[d];
-    }
-    E_out[i] = E;
-    // B = dE/dA
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-        R An[LM], Bn[LM];
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) An[lm] = A_in[((long)i * NA + n) * LM + lm];
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) Bn[lm] = R(2) * e[NR + (lm_degree<LM>(lm) - 1) * NA + n] * An[lm];
-        if (Sh::H4) {
-            R g4[5];
-            q4_grad<R>(&An[3], g4);
-            const R e4 = e[NR + Sh::L * NA + n];
-#pragma unroll
-            for (int m = 0; m < 5; ++m) Bn[3 + m] += e4 * g4[m];
-        }
-        if (Sh::H5) {
-            const R P = An[0] * An[0] + An[1] * An[1] + An[2] * An[2];
-            const R e5 = e[NR + (Sh::L + (Sh::H4 ? 1 : 0)) * NA + n];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) Bn[m] += e5 * R(4) * P * An[m];
-        }
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) B_out[((long)i * NA + n) * LM + lm] = Bn[lm];
-    }
-    // radial force coefficients for every neighbour species
-    for (int b = 0; b < T; ++b) {
-        const R* __restrict__ cR = theta + (long)((a * T + b) * NR) * KR;
-#pragma unroll
-        for (int kk = 0; kk < KR; ++kk) {
-            R s = R(0);
-#pragma unroll
-            for (int n = 0; n < NR; ++n) s += e[n] * cR[n * KR + kk];
-            eps_out[((long)i * T + b) * KR + kk] = s;
-        }
+            for (int o = 0; o < OWN; ++o) {
+                const int lm = lane + S * o;
+                if (lm < LM) A_out[((long)i * NA + n) * LM + lm] = acc[n][o];
+            }
     }
 }
 
 // ------------------------------------------------------------------- force
 
-// F_k = sum_{j in N(k)} (dE_k/dr_kj - dE_j/dr_jk) (gather form over k's row)
-// and the per-atom virial -1/2 sum_j r_kj (x) (that pair force), which sums
-// over a structure to W = -sum_{i,j} r_ij (x) dE_i/dr_ij.
+// h_ij = dE_i/dr_ij for every pair of atom i's row, from atom i's own
+// B = dE_i/dA and eps = radial force coefficients only (one direction per
+// pair): the atom's own-direction sum sum_j h_ij, its virial
+// -sum_j r_ij (x) h_ij, and -h_ij written into the slot of the reverse pair
+// (j, i), so that k_force_gather completes F_j = sum h_jk + sum (-h_kj) with
+// contiguous reads and no atomics.
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
 k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
         const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-        const R* __restrict__ B_in, const R* __restrict__ eps_in, R* __restrict__ F_out, R* __restrict__ Wat_out) {
+        const int* __restrict__ reverse, const R* __restrict__ B_in, const R* __restrict__ eps_in,
+        Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
     constexpr int NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM;
+    constexpr int TEAMS = kBlock / S;
+    __shared__ R Bsh[TEAMS][NA * LM];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = blockIdx.x * (kBlock / S) + team;
+    const int i = blockIdx.x * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
     const int a = live ? types[i] : 0;
     int64_t p = live ? row[i] : 0;
+    for (int x = lane; x < NA * LM; x += S) Bsh[team][x] = live ? B_in[(long)i * NA * LM + x] : R(0);
+    __syncthreads();
+    const R* Bk = Bsh[team];
     R F[3] = {R(0), R(0), R(0)};
     R Wv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) Wv[c] = R(0);
-    const R* __restrict__ Bk = B_in + (long)i * NA * LM;
-
     for (int b = 0; b < T; ++b) {
         const int tot = live ? seg[(i * T + b) * 2] : 0;
         const int ang = live ? seg[(i * T + b) * 2 + 1] : 0;
         R epsk[KR];
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) epsk[kk] = live ? eps_in[((long)i * T + b) * KR + kk] : R(0);
-        const R* __restrict__ cAab = theta + dm.offA + (long)((a * T + b) * NA) * KA;
-        const R* __restrict__ cAba = theta + dm.offA + (long)((b * T + a) * NA) * KA;
+        const R* __restrict__ cA = theta + dm.offA + (long)((a * T + b) * NA) * KA;
         for (int k = lane; k < tot; k += S) {
             const Rec<R> pr = pairs[p + k];
-            const int j = rec_j(pr);
             const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
             const R ir = R(1) / r;
             const R u[3] = {pr.x * ir, pr.y * ir, pr.z * ir};
             R f[KR], fp[KR];
             cheb_basis<R, KR, true>(r, rcR, irR, f, fp);
-            const R* __restrict__ epsj = eps_in + ((long)j * T + a) * KR;
-            R s = R(0);
+            R sr = R(0);
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) s += (epsk[kk] + epsj[kk]) * fp[kk];
-            R fv[3] = {s * u[0], s * u[1], s * u[2]};
+            for (int kk = 0; kk < KR; ++kk) sr += epsk[kk] * fp[kk];
+            R hv[3] = {sr * u[0], sr * u[1], sr * u[2]};
             if (k < ang) {
                 R fa[KA], fap[KA];
                 cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
@@ -263,24 +220,18 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
                 R c[LM], cp[LM];
 #pragma unroll
                 for (int lm = 0; lm < LM; ++lm) c[lm] = cp[lm] = R(0);
-                const R* __restrict__ Bj = B_in + (long)j * NA * LM;
 #pragma unroll
                 for (int n = 0; n < NA; ++n) {
-                    R g1 = R(0), gp1 = R(0), g2 = R(0), gp2 = R(0);
+                    R g = R(0), gp = R(0);
 #pragma unroll
                     for (int kk = 0; kk < KA; ++kk) {
-                        const R c1 = cAab[n * KA + kk], c2 = cAba[n * KA + kk];
-                        g1 += c1 * fa[kk];
-                        gp1 += c1 * fap[kk];
-                        g2 += c2 * fa[kk];
-                        gp2 += c2 * fap[kk];
+                        g += cA[n * KA + kk] * fa[kk];
+                        gp += cA[n * KA + kk] * fap[kk];
                     }
 #pragma unroll
                     for (int lm = 0; lm < LM; ++lm) {
-                        const R bk = Bk[n * LM + lm];
-                        const R bj = (lm_degree<LM>(lm) & 1) ? -Bj[n * LM + lm] : Bj[n * LM + lm];
-                        c[lm] += bk * g1 + bj * g2;
-                        cp[lm] += bk * gp1 + bj * gp2;
+                        c[lm] += Bk[n * LM + lm] * g;
+                        cp[lm] += Bk[n * LM + lm] * gp;
                     }
                 }
                 R sY = R(0), lY = R(0), G[3] = {R(0), R(0), R(0)};
@@ -293,15 +244,24 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
                     G[2] += c[lm] * Yg[lm].z;
                 }
 #pragma unroll
-                for (int d = 0; d < 3; ++d) fv[d] += sY * u[d] + (G[d] - lY * u[d]) * ir;
+                for (int d = 0; d < 3; ++d) hv[d] += sY * u[d] + (G[d] - lY * u[d]) * ir;
+            }
+            const int q = reverse[p + k];
+            if (q >= 0) {
+                Rec<R> ho;
+                ho.x = -hv[0];
+                ho.y = -hv[1];
+                ho.z = -hv[2];
+                ho.w = R(0);
+                h_in[q] = ho;  // -dE_i/dr_ij is the pair's contribution to F_j
             }
             const R rv[3] = {pr.x, pr.y, pr.z};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) F[d] += fv[d];
+            for (int d = 0; d < 3; ++d) F[d] += hv[d];
 #pragma unroll
             for (int al = 0; al < 3; ++al)
 #pragma unroll
-                for (int be = 0; be < 3; ++be) Wv[al * 3 + be] -= R(0.5) * rv[al] * fv[be];
+                for (int be = 0; be < 3; ++be) Wv[al * 3 + be] -= rv[al] * hv[be];
         }
         p += tot;
     }
@@ -312,26 +272,57 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
     if (live) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            if (d % S == lane) F_out[(long)i * 3 + d] = F[d];
+            if (d % S == lane) Fown_out[(long)i * 3 + d] = F[d];
 #pragma unroll
         for (int c = 0; c < 9; ++c)
             if (c % S == lane) Wat_out[(long)i * 9 + c] = Wv[c];
     }
 }
 
+// F_i = (own-direction sum) + sum_{p in row i} h_in[p]: team of S lanes per
+// atom over its (contiguous) row, team sum in fixed shuffle order. Slots of
+// pairs without a reverse partner were never written and are skipped.
+template <typename R, int S>
+__global__ void __launch_bounds__(kBlock)
+k_force_gather(int Na, const int64_t* __restrict__ row, const int* __restrict__ reverse,
+               const Rec<R>* __restrict__ h_in, const R* __restrict__ Fown, R* __restrict__ F_out) {
+    const int team = threadIdx.x / S, lane = threadIdx.x % S;
+    const int i = blockIdx.x * (kBlock / S) + team;
+    const bool live = i < Na;
+    const int64_t p0 = live ? row[i] : 0, p1 = live ? row[i + 1] : 0;
+    R f[3] = {R(0), R(0), R(0)};
+    for (int64_t p = p0 + lane; p < p1; p += S) {
+        if (reverse[p] < 0) continue;  // unpaired (|r| at the cutoff): slot never written
+        const Rec<R> a = h_in[p];
+        f[0] += a.x;
+        f[1] += a.y;
+        f[2] += a.z;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f[d] = team_sum<S>(f[d]);
+    if (live && lane < 3) F_out[(long)i * 3 + lane] = Fown[(long)i * 3 + lane] + (lane == 0 ? f[0] : (lane == 1 ? f[1] : f[2]));
+}
+
 // ----------------------------------------------------------------- tangent
 
 // Directional derivative of the descriptor along v_ij = u_i - u_j - U_s^T r_ij:
-// dq (radial and invariants), dA[n][lm], and S1[b][k] = sum_{j in b} (v.r^) f_k'.
+// dq (radial and invariants), dA[n][lm] = sum_j [g_n' (v.r^) Y_lm + g_n v.dY_lm],
+// and S1[b][k] = sum_{j in b} (v.r^) f_k'. Angular pairs go through the team
+// exchange (two terms per pair); each lane owns the moments lm = lane + S*o.
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
 k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types,
           const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row, const int* __restrict__ seg,
           const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar, const double* __restrict__ Ubar,
           const R* __restrict__ A_in, R* __restrict__ dq_out, R* __restrict__ dA_out, R* __restrict__ S1_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D;
+    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D, L = Sh::L;
+    using X = MomentExchange<R, NA, LM, S>;
+    constexpr int OWN = X::OWN, TEAMS = kBlock / S;
+    constexpr int DANG = NA * (L + (Sh::H4 ? 1 : 0) + (Sh::H5 ? 1 : 0));
+    __shared__ R xbuf[TEAMS * X::TEAM_FLOATS];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = blockIdx.x * (kBlock / S) + team;
+    R* tbuf = xbuf + team * X::TEAM_FLOATS;
+    const int i = blockIdx.x * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
@@ -344,13 +335,13 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
 #pragma unroll
     for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
     R dqR[NR];
-    R dA[NA][LM];
 #pragma unroll
     for (int n = 0; n < NR; ++n) dqR[n] = R(0);
+    R acc[NA][OWN];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
-        for (int lm = 0; lm < LM; ++lm) dA[n][lm] = R(0);
+        for (int o = 0; o < OWN; ++o) acc[n][o] = R(0);
 
     for (int b = 0; b < T; ++b) {
         const int tot = live ? seg[(i * T + b) * 2] : 0;
@@ -359,46 +350,57 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
         R Sb[KR];
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) Sb[kk] = R(0);
-        for (int k = lane; k < tot; k += S) {
-            const Rec<R> pr = pairs[p + k];
-            const int j = rec_j(pr);
-            const R rv[3] = {pr.x, pr.y, pr.z};
-            R v[3];
+        for (int base = 0; base < tot; base += S) {
+            const int k = base + lane;
+            const bool angb = base < ang;  // team-uniform: this batch starts inside the angular prefix
+            R gpv[NA], g[NA], Y[LM], vdY[LM];
 #pragma unroll
-            for (int be = 0; be < 3; ++be)
-                v[be] = ui[be] - ubar[(long)j * 3 + be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
-            const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
-            const R ir = R(1) / r;
-            const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
-            const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
-            R f[KR], fp[KR];
-            cheb_basis<R, KR, true>(r, rcR, irR, f, fp);
+            for (int n = 0; n < NA; ++n) gpv[n] = g[n] = R(0);
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) Sb[kk] += vu * fp[kk];
-            if (k < ang) {
-                R fa[KA], fap[KA];
-                cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
-                const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
-                D1<R> Yd[LM];
-                solid_harmonics<D1<R>, R, Sh::L>(dx, dy, dz, Yd);
-                R Y[LM], vdY[LM];
+            for (int lm = 0; lm < LM; ++lm) Y[lm] = vdY[lm] = R(0);
+            if (k < tot) {
+                const Rec<R> pr = pairs[p + k];
+                const int j = rec_j(pr);
+                const R rv[3] = {pr.x, pr.y, pr.z};
+                R v[3];
 #pragma unroll
-                for (int lm = 0; lm < LM; ++lm) {
-                    Y[lm] = Yd[lm].v;
-                    vdY[lm] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
-                }
+                for (int be = 0; be < 3; ++be)
+                    v[be] = ui[be] - ubar[(long)j * 3 + be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
+                const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+                const R ir = R(1) / r;
+                const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
+                const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
+                R f[KR], fp[KR];
+                cheb_basis<R, KR, true>(r, rcR, irR, f, fp);
 #pragma unroll
-                for (int n = 0; n < NA; ++n) {
-                    R g = R(0), gp = R(0);
+                for (int kk = 0; kk < KR; ++kk) Sb[kk] += vu * fp[kk];
+                if (k < ang) {
+                    R fa[KA], fap[KA];
+                    cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
+                    const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
+                    D1<R> Yd[LM];
+                    solid_harmonics<D1<R>, R, L>(dx, dy, dz, Yd);
 #pragma unroll
-                    for (int kk = 0; kk < KA; ++kk) {
-                        g += cA[n * KA + kk] * fa[kk];
-                        gp += cA[n * KA + kk] * fap[kk];
+                    for (int lm = 0; lm < LM; ++lm) {
+                        Y[lm] = Yd[lm].v;
+                        vdY[lm] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
                     }
-                    const R gpv = gp * vu;
 #pragma unroll
-                    for (int lm = 0; lm < LM; ++lm) dA[n][lm] += gpv * Y[lm] + g * vdY[lm];
+                    for (int n = 0; n < NA; ++n) {
+                        R gg = R(0), gp = R(0);
+#pragma unroll
+                        for (int kk = 0; kk < KA; ++kk) {
+                            gg += cA[n * KA + kk] * fa[kk];
+                            gp += cA[n * KA + kk] * fap[kk];
+                        }
+                        g[n] = gg;
+                        gpv[n] = gp * vu;
+                    }
                 }
+            }
+            if (angb) {
+                X::accumulate(tbuf, lane, gpv, Y, acc);
+                X::accumulate(tbuf, lane, g, vdY, acc);
             }
         }
         p += tot;
@@ -415,105 +417,601 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
                 if (kk % S == lane) S1_out[((long)i * T + b) * KR + kk] = Sb[kk];
         }
     }
+    // invariant tangents: contractions with the atom's own moments A, split
+    // over the owned harmonics and summed over the team
+    R part[DANG];
+#pragma unroll
+    for (int x = 0; x < DANG; ++x) part[x] = R(0);
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+        R An[OWN];
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int lm = lane + S * o;
+            An[o] = (live && lm < LM) ? A_in[((long)i * NA + n) * LM + lm] : R(0);
+        }
+#pragma unroll
+        for (int l = 1; l <= L; ++l)
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) {
+                const int lm = lane + S * o;
+                if (lm < LM && lm_degree<LM>(lm) == l) part[(l - 1) * NA + n] += R(2) * An[o] * acc[n][o];
+            }
+        if (Sh::H4) {
+            R a2[5], g4[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) a2[m] = live ? A_in[((long)i * NA + n) * LM + 3 + m] : R(0);
+            q4_grad<R>(a2, g4);
+#pragma unroll
+            for (int o = 0; o < OWN; ++o)
+#pragma unroll
+                for (int m = 0; m < 5; ++m)
+                    if (lane + S * o == 3 + m) part[L * NA + n] += g4[m] * acc[n][o];
+        }
+        if (Sh::H5) {
+            R P = R(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const R am = live ? A_in[((long)i * NA + n) * LM + m] : R(0);
+                P += am * am;
+            }
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) {
+                const int lm = lane + S * o;
+                if (lm < 3) part[(L + (Sh::H4 ? 1 : 0)) * NA + n] += R(4) * P * An[o] * acc[n][o];
+            }
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < DANG; ++x) part[x] = team_sum<S>(part[x]);
+    if (!live) return;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (d % S != lane) continue;
+        dq_out[(long)i * D + d] = d < NR ? dqR[d] : part[d - NR];
+    }
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
-        for (int lm = 0; lm < LM; ++lm) dA[n][lm] = team_sum<S>(dA[n][lm]);
-    if (!live) return;
-    R dq[D];
-#pragma unroll
-    for (int n = 0; n < NR; ++n) dq[n] = dqR[n];
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-        R An[LM];
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) An[lm] = A_in[((long)i * NA + n) * LM + lm];
-#pragma unroll
-        for (int l = 1; l <= Sh::L; ++l) {
-            R s2 = R(0);
-#pragma unroll
-            for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) s2 += An[lm] * dA[n][lm];
-            dq[NR + (l - 1) * NA + n] = R(2) * s2;
+        for (int o = 0; o < OWN; ++o) {
+            const int lm = lane + S * o;
+            if (lm < LM) dA_out[((long)i * NA + n) * LM + lm] = acc[n][o];
         }
+}
+
+// -------------------------------------------------- angular coefficient grad
+
+// dL/dc_A[a][b][n][k] = sum_{i in a} sum_{j in b, angular}
+//     [ f_k P_n + f_k' R_n ],  P_n = sum_lm (Bp_nlm Y_lm + Q_nlm v.dY_lm),
+//     R_n = (v.r^) sum_lm Q_nlm Y_lm,  Q = B = dE_i/dA.
+// The atom's Bp and Q sit in LDS; each lane evaluates one pair of a batch and
+// the team exchanges (P, f) and (R, f') so each lane owns k = lane + S*o.
+// Per neighbour species the team's sums go to a team slot and are added into
+// the block accumulator in team order (bitwise repeatable); one partial row
+// (double) per block over a grid-stride loop of atom tiles.
+template <typename R, class Sh, int S>
+struct CoeffGradSmem {
+    static constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, TEAMS = kBlock / S;
+    using X = MomentExchange<R, NA, KA, S>;
+    static size_t bytes(int T) {
+        return sizeof(R) * (size_t(T) * T * NA * KA + size_t(TEAMS) * NA * KA + size_t(TEAMS) * 2 * NA * LM +
+                            size_t(TEAMS) * X::TEAM_FLOATS) +
+               sizeof(int) * TEAMS;
+    }
+};
+
+template <typename R, class Sh, int S>
+__global__ void __launch_bounds__(kBlock)
+k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
+                     const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
+                     const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ Bp_in,
+                     const R* __restrict__ Q_in, double* __restrict__ partial) {
+    constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L;
+    using X = MomentExchange<R, NA, KA, S>;
+    constexpr int OWN = X::OWN, NK = NA * KA, TEAMS = kBlock / S;
+    extern __shared__ unsigned char smem_raw[];
+    const int T = dm.T;
+    const int G_len = T * T * NK;
+    R* G = reinterpret_cast<R*>(smem_raw);
+    R* slot = G + G_len;                      // [TEAMS][NK]
+    R* BQ = slot + TEAMS * NK;                // [TEAMS][2][NA][LM]
+    R* xb = BQ + TEAMS * 2 * NA * LM;         // [TEAMS][exchange]
+    int* team_type = reinterpret_cast<int*>(xb + TEAMS * X::TEAM_FLOATS);
+    for (int x = threadIdx.x; x < G_len; x += kBlock) G[x] = R(0);
+    const int team = threadIdx.x / S, lane = threadIdx.x % S;
+    R* myBp = BQ + team * 2 * NA * LM;
+    R* myQ = myBp + NA * LM;
+    R* tbuf = xb + team * X::TEAM_FLOATS;
+    const R rcA = R(dm.rcA), irA = R(1.0 / dm.rcA);
+    const int tiles = (Na + TEAMS - 1) / TEAMS;
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int i = tile * TEAMS + team;
+        const bool live = i < Na;
+        const int a = live ? types[i] : 0;
+        const int s = live ? atom_struct[i] : 0;
+        int64_t p = live ? row[i] : 0;
+        R ui[3], U[9];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ui[d] = live ? ubar[(long)i * 3 + d] : R(0);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
+        __syncthreads();
+        for (int x = lane; x < NA * LM; x += S) {
+            myBp[x] = live ? Bp_in[(long)i * NA * LM + x] : R(0);
+            myQ[x] = live ? Q_in[(long)i * NA * LM + x] : R(0);
+        }
+        __syncthreads();
+        for (int b = 0; b < T; ++b) {
+            const int tot = live ? seg[(i * T + b) * 2] : 0;
+            const int ang = live ? seg[(i * T + b) * 2 + 1] : 0;
+            R acc[NA][OWN];
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int o = 0; o < OWN; ++o) acc[n][o] = R(0);
+            for (int base = 0; base < ang; base += S) {
+                const int k = base + lane;
+                R P[NA], Rn[NA], fa[KA], fap[KA];
+#pragma unroll
+                for (int n = 0; n < NA; ++n) P[n] = Rn[n] = R(0);
+#pragma unroll
+                for (int kk = 0; kk < KA; ++kk) fa[kk] = fap[kk] = R(0);
+                if (k < ang) {
+                    const Rec<R> pr = pairs[p + k];
+                    const int j = rec_j(pr);
+                    const R rv[3] = {pr.x, pr.y, pr.z};
+                    R v[3];
+#pragma unroll
+                    for (int be = 0; be < 3; ++be)
+                        v[be] = ui[be] - ubar[(long)j * 3 + be] -
+                                (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
+                    const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+                    const R ir = R(1) / r;
+                    const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
+                    const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
+                    cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
+                    const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
+                    D1<R> Yd[LM];
+                    solid_harmonics<D1<R>, R, L>(dx, dy, dz, Yd);
+#pragma unroll
+                    for (int n = 0; n < NA; ++n) {
+                        R pn = R(0), rn = R(0);
+#pragma unroll
+                        for (int lm = 0; lm < LM; ++lm) {
+                            const R y = Yd[lm].v;
+                            const R vdy = (Yd[lm].d - R(lm_degree<LM>(lm)) * y * vu) * ir;
+                            const R q = myQ[n * LM + lm];
+                            pn += myBp[n * LM + lm] * y + q * vdy;
+                            rn += q * y;
+                        }
+                        P[n] = pn;
+                        Rn[n] = rn * vu;
+                    }
+                }
+                X::accumulate(tbuf, lane, P, fa, acc);
+                X::accumulate(tbuf, lane, Rn, fap, acc);
+            }
+            p += tot;
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int o = 0; o < OWN; ++o) {
+                    const int kk = lane + S * o;
+                    if (kk < KA) slot[team * NK + n * KA + kk] = live ? acc[n][o] : R(0);
+                }
+            if (lane == 0) team_type[team] = a;
+            __syncthreads();
+            for (int x = threadIdx.x; x < NK; x += kBlock)
+                for (int tm = 0; tm < TEAMS; ++tm) G[(team_type[tm] * T + b) * NK + x] += slot[tm * NK + x];
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < G_len; x += kBlock) partial[(long)blockIdx.x * G_len + x] = double(G[x]);
+}
+
+// ------------------------------------------ network and radial coefficient grad
+
+// Work item b of the species-sorted atom list: chunk k of species t, i.e.
+// sorted positions [soff[t] + k*chunk, min(soff[t+1], soff[t] + (k+1)*chunk)).
+// Items beyond the last chunk get t = -1.
+__device__ __forceinline__ void species_chunk(const int64_t* __restrict__ soff, int T, int chunk, int b, int* t_out,
+                                              long* lo, long* hi) {
+    *t_out = -1;
+    for (int t = 0; t < T; ++t) {
+        const long n = soff[t + 1] - soff[t];
+        const int c = int((n + chunk - 1) / chunk);
+        if (b < c) {
+            *t_out = t;
+            *lo = soff[t] + long(b) * chunk;
+            *hi = min(soff[t + 1], *lo + chunk);
+            return;
+        }
+        b -= c;
+    }
+}
+
+// Matrix-core tile C[M][M] += A[M][KPI] B[KPI][M] of one wavefront.
+// FP32: v_mfma_f32_32x32x2f32 (M = 32, K = 2 per instruction);
+// FP64: v_mfma_f64_16x16x4f64 (M = 16, K = 4 per instruction).
+// Operand lane l supplies A[l mod M][l / M] and B[l / M][l mod M]; accumulator
+// register v of lane l holds C[c_row(l, v)][l mod M].
+template <typename R>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+    static constexpr int M = 32, KPI = 2, NV = 16;
+    typedef float Acc __attribute__((ext_vector_type(16)));
+    __device__ static Acc mma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+    __device__ static int c_row(int lane, int v) { return (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2); }
+};
+
+template <>
+struct Mfma<double> {
+    static constexpr int M = 16, KPI = 4, NV = 4;
+    typedef double Acc __attribute__((ext_vector_type(4)));
+    __device__ static Acc mma(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int c_row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+// For the per-atom outer products sum_i X1_i (x) Y1_i + X2_i (x) Y2_i the K
+// slots of one instruction are (atom, term) pairs: KPI / 2 atoms per instruction.
+template <typename R>
+struct OuterMma : Mfma<R> {
+    static constexpr int ATOMS = Mfma<R>::KPI / 2;
+    __device__ static int slot_atom(int lane) { return (lane / Mfma<R>::M) >> 1; }
+    __device__ static int slot_term(int lane) { return (lane / Mfma<R>::M) & 1; }
+};
+
+// One partial row per work item (a chunk of atoms of one species a):
+//   row[0] = a (or -1 for an empty item), then W1 = (D+2) H + T NR KR columns:
+//   W0[mu][nu] = sum_i alpha_mu (s q)_nu + beta_mu (s dq)_nu     (matrix cores),
+//   b0[mu] = -sum_i alpha_mu, w1[mu] = sum_i gamma_mu,
+//   c_R[a][b][n][k] = sum_i abar_n S0[b][k] + e_n S1[b][k]        (matrix cores).
+// Each wave accumulates its share of the chunk's atoms per output tile; the
+// four wave tiles are added in wave order through LDS.
+template <typename R, class Sh>
+__global__ void __launch_bounds__(kBlock)
+k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict__ order,
+             const int64_t* __restrict__ soff, int chunk, const R* __restrict__ q_in, const R* __restrict__ dq_in,
+             const R* __restrict__ abar, const R* __restrict__ e_in, const R* __restrict__ alpha,
+             const R* __restrict__ beta, const R* __restrict__ gam, const R* __restrict__ S0,
+             const R* __restrict__ S1, double* __restrict__ partial) {
+    using MM = OuterMma<R>;
+    constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D;
+    constexpr int WAVES = kBlock / 64;
+    __shared__ R tile_buf[WAVES][M * M];
+    const int T = dm.T, H = dm.H, TK = T * KR;
+    const int W1 = (D + 2) * H + T * NR * KR;
+    double* __restrict__ rowp = partial + (long)blockIdx.x * (W1 + 1);
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, chunk, blockIdx.x, &a, &lo, &hi);
+    if (threadIdx.x == 0) rowp[0] = double(a);
+    if (a < 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int srow = lane % M, satom = MM::slot_atom(lane), sterm = MM::slot_term(lane);
+    // this wave's atoms: sorted positions lo + wave, lo + wave + WAVES, ...
+    const int tilesH = (H + M - 1) / M, tilesD = (D + M - 1) / M;
+    const int tilesR = (NR + M - 1) / M, tilesC = (TK + M - 1) / M;
+    const int ntiles = tilesH * tilesD + tilesR * tilesC;
+    for (int tl = 0; tl < ntiles; ++tl) {
+        const bool wtile = tl < tilesH * tilesD;
+        const int r0 = (wtile ? tl / tilesD : (tl - tilesH * tilesD) / tilesC) * M;
+        const int c0 = (wtile ? tl % tilesD : (tl - tilesH * tilesD) % tilesC) * M;
+        const int rr = r0 + srow, cc = c0 + srow;
+        typename MM::Acc acc;
+#pragma unroll
+        for (int v = 0; v < MM::NV; ++v) acc[v] = R(0);
+        const R sc = (wtile && cc < D) ? qscale[cc] : R(1);
+        // batches of U instructions: all operand loads first, then the MFMAs
+        constexpr int U = 8;
+        const long stride = long(WAVES) * MM::ATOMS;
+        for (long s0 = lo + long(wave) * MM::ATOMS; s0 < hi; s0 += stride * U) {
+            R xs[U], ys[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long sa = s0 + u * stride + satom;
+                xs[u] = ys[u] = R(0);
+                if (sa < hi) {
+                    const long i = order[sa];
+                    if (wtile) {
+                        if (rr < H) xs[u] = (sterm ? beta : alpha)[i * H + rr];
+                        if (cc < D) ys[u] = sc * (sterm ? dq_in : q_in)[i * D + cc];
+                    } else {
+                        if (rr < NR) xs[u] = (sterm ? e_in : abar)[i * D + rr];
+                        if (cc < TK) ys[u] = (sterm ? S1 : S0)[i * TK + cc];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = MM::mma(xs[u], ys[u], acc);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < MM::NV; ++v) tile_buf[wave][MM::c_row(lane, v) * M + (lane % M)] = acc[v];
+        __syncthreads();
+        for (int x = threadIdx.x; x < M * M; x += kBlock) {
+            R sum = R(0);
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) sum += tile_buf[w][x];
+            const int r = r0 + x / M, c = c0 + x % M;
+            if (wtile) {
+                if (r < H && c < D) rowp[1 + r * D + c] = double(sum);
+            } else if (r < NR && c < TK) {
+                const int b = c / KR, k = c % KR;
+                rowp[1 + (D + 2) * H + (b * NR + r) * KR + k] = double(sum);
+            }
+        }
+    }
+    // b0 and w1 columns: sums over the chunk, lanes over neurons, waves over
+    // atoms, wave sums added in wave order
+    R* red = &tile_buf[0][0];
+    for (int mu0 = 0; mu0 < H; mu0 += 64) {
+        const int mu = mu0 + lane;
+        R sa = R(0), sg = R(0);
+        if (mu < H)
+            for (long s = lo + wave; s < hi; s += WAVES) {
+                const long i = order[s];
+                sa += alpha[i * H + mu];
+                sg += gam[i * H + mu];
+            }
+        __syncthreads();
+        red[wave * 64 + lane] = sa;
+        red[(WAVES + wave) * 64 + lane] = sg;
+        __syncthreads();
+        if (wave == 0 && mu < H) {
+            R ta = R(0), tg = R(0);
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                ta += red[w * 64 + lane];
+                tg += red[(WAVES + w) * 64 + lane];
+            }
+            rowp[1 + H * D + mu] = -double(ta);
+            rowp[1 + H * D + H + mu] = double(tg);
+        }
+    }}
+
+// ------------------------------------------------- network on matrix cores
+
+// One 64-lane block per tile of M atoms of one species (species-sorted list).
+// The hidden pre-activations are computed transposed, a^T = W0 (s q)^T, so the
+// M x M accumulator holds hidden rows x atom columns and each atom's values
+// sit in the lanes that share its column. The second product of each pass
+// (W0^T times a per-hidden-unit factor) is fed through an LDS transpose.
+
+// dE_i/dA[n][lm] for the moments of atom row `ia` (lane share n = kk, kk + nsub, ...).
+template <typename R, class Sh>
+__device__ __forceinline__ void moments_adjoint(const R* e, const R* __restrict__ A_in, long ia, int kk, int nsub,
+                                                R* __restrict__ B_out) {
+    constexpr int NR = Sh::NR, NA = Sh::NA, LM = Sh::LM;
+    for (int n = kk; n < NA; n += nsub) {
+        R An[LM], Bn[LM];
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) An[lm] = A_in[(ia * NA + n) * LM + lm];
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) Bn[lm] = R(2) * e[NR + (lm_degree<LM>(lm) - 1) * NA + n] * An[lm];
         if (Sh::H4) {
             R g4[5];
             q4_grad<R>(&An[3], g4);
-            R s4 = R(0);
+            const R e4 = e[NR + Sh::L * NA + n];
 #pragma unroll
-            for (int m = 0; m < 5; ++m) s4 += g4[m] * dA[n][3 + m];
-            dq[NR + Sh::L * NA + n] = s4;
+            for (int m = 0; m < 5; ++m) Bn[3 + m] += e4 * g4[m];
         }
         if (Sh::H5) {
             const R P = An[0] * An[0] + An[1] * An[1] + An[2] * An[2];
-            const R dd = An[0] * dA[n][0] + An[1] * dA[n][1] + An[2] * dA[n][2];
-            dq[NR + (Sh::L + (Sh::H4 ? 1 : 0)) * NA + n] = R(4) * P * dd;
+            const R e5 = e[NR + (Sh::L + (Sh::H4 ? 1 : 0)) * NA + n];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) Bn[m] += e5 * R(4) * P * An[m];
         }
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) B_out[(ia * NA + n) * LM + lm] = Bn[lm];
     }
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-        if (d % S == lane) dq_out[(long)i * D + d] = dq[d];
-#pragma unroll
-    for (int n = 0; n < NA; ++n)
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm)
-            if ((n * LM + lm) % S == lane) dA_out[((long)i * NA + n) * LM + lm] = dA[n][lm];
 }
 
-// ------------------------------------------------------------- network bwd
-
-// For Psi = sum_i ebar_s E_i + e(q_i) . dq_i: per-atom factors of the network
-// weight gradients (alpha, beta, gamma), abar = dPsi/dq and
-// Bp = dPsi/dA[n][lm] (the angular moments' adjoint).
+// E_i, e_i = dE_i/dq_i and tanh activations (Eqs. 2-3), then per atom
+// B = dE_i/dA[n][lm] and the radial force coefficients eps[b][k] = sum_n e_n c_R[a][b][n][k].
 template <typename R, class Sh>
-__global__ void __launch_bounds__(kBlock)
-k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
-                   const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
-                   const double* __restrict__ ebar_s, const R* __restrict__ q_in, const R* __restrict__ dq_in,
-                   const R* __restrict__ e_in, const R* __restrict__ t_in, const R* __restrict__ A_in,
-                   const R* __restrict__ dA_in, R* __restrict__ abar_out, R* __restrict__ alpha_out,
-                   R* __restrict__ beta_out, R* __restrict__ gamma_out, R* __restrict__ Bp_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, LM = Sh::LM, D = Sh::D;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Na) return;
-    const int H = dm.H;
-    const int a = types[i];
-    const R eb = R(ebar_s[atom_struct[i]]);
-    R dqs[D], z[D];
+__global__ void __launch_bounds__(64)
+k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
+                  const int* __restrict__ order, const int64_t* __restrict__ soff, const R* __restrict__ q_in,
+                  const R* __restrict__ A_in, R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out,
+                  R* __restrict__ B_out, R* __restrict__ eps_out) {
+    using MM = Mfma<R>;
+    constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D, NR = Sh::NR, KR = Sh::KR;
+    constexpr int DT = (D + M - 1) / M, DK = (D + KPI - 1) / KPI;
+    __shared__ R cbuf[M * M];
+    __shared__ R ebuf[M * D];
+    const int T = dm.T, H = dm.H;
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, M, blockIdx.x, &a, &lo, &hi);
+    if (a < 0) return;
+    const int lane = threadIdx.x, j = lane % M, kk = lane / M;
+    const long ia = (lo + j < hi) ? long(order[lo + j]) : -1;
+    const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
+    const R* __restrict__ b0 = W0 + (long)H * D;
+    const R* __restrict__ w1 = b0 + H;
+    R qk[DK];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        dqs[d] = dq_in[(long)i * D + d] * qscale[d];
-        z[d] = R(0);
+    for (int s = 0; s < DK; ++s) {
+        const int k = s * KPI + kk;
+        qk[s] = (ia >= 0 && k < D) ? qscale[k] * q_in[ia * D + k] : R(0);
     }
+    typename MM::Acc eacc[DT];
+#pragma unroll
+    for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) eacc[dt][v] = R(0);
+    R Ej = R(0);
+    for (int mu0 = 0; mu0 < H; mu0 += M) {
+        typename MM::Acc acc;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = R(0);
+        const int mrow = mu0 + j;
+#pragma unroll
+        for (int s = 0; s < DK; ++s) {
+            const int k = s * KPI + kk;
+            const R x = (mrow < H && k < D) ? W0[(long)mrow * D + k] : R(0);
+            acc = MM::mma(x, qk[s], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int r = MM::c_row(lane, v), mu = mu0 + r;
+            R c = R(0);
+            if (mu < H) {
+                const R t = tanh_<R>(acc[v] - b0[mu]);
+                if (ia >= 0) t_out[ia * H + mu] = t;
+                const R w = w1[mu];
+                Ej += w * t;
+                c = w * (R(1) - t * t);
+            }
+            cbuf[r * M + j] = c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int dt = 0; dt < DT; ++dt) {
+            const int nu = dt * M + j;
+#pragma unroll
+            for (int s = 0; s < M / KPI; ++s) {
+                const int k = s * KPI + kk;
+                const R x = (nu < D && mu0 + k < H) ? W0[(long)(mu0 + k) * D + nu] : R(0);
+                eacc[dt] = MM::mma(x, cbuf[k * M + j], eacc[dt]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = M; o < 64; o <<= 1) Ej += __shfl_xor(Ej, o, 64);
+    if (kk == 0 && ia >= 0) E_out[ia] = Ej - theta[dm.offB1];
+#pragma unroll
+    for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int nu = dt * M + MM::c_row(lane, v);
+            if (nu < D) {
+                const R val = qscale[nu] * eacc[dt][v];
+                ebuf[j * D + nu] = val;
+                if (ia >= 0) e_out[ia * D + nu] = val;
+            }
+        }
+    __syncthreads();
+    if (ia < 0) return;
+    const R* e = ebuf + j * D;
+    constexpr int nsub = 64 / M;
+    moments_adjoint<R, Sh>(e, A_in, ia, kk, nsub, B_out);
+    for (int bk = kk; bk < T * KR; bk += nsub) {
+        const int b = bk / KR, k = bk % KR;
+        const R* __restrict__ cR = theta + (long)((a * T + b) * NR) * KR + k;
+        R sum = R(0);
+#pragma unroll
+        for (int n = 0; n < NR; ++n) sum += e[n] * cR[n * KR];
+        eps_out[(ia * T + b) * KR + k] = sum;
+    }
+}
+
+// For Psi = sum_i ebar_s E_i + e(q_i) . dq_i (the force/virial adjoint): the
+// Hessian-vector product da = W0 (s dq), per-unit weight-gradient factors
+// alpha = w1 s'(ebar - 2 t da), beta = w1 s', gamma = ebar t + s' da,
+// abar = dPsi/dq = ebar e + s (W0^T (-2 w1 t s' da)), and per atom
+// Bp = dPsi/dA[n][lm].
+template <typename R, class Sh>
+__global__ void __launch_bounds__(64)
+k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
+                   const int* __restrict__ order, const int64_t* __restrict__ soff, const int* __restrict__ atom_struct,
+                   const double* __restrict__ ebar_s, const R* __restrict__ dq_in, const R* __restrict__ e_in,
+                   const R* __restrict__ t_in, const R* __restrict__ A_in, const R* __restrict__ dA_in,
+                   R* __restrict__ abar_out, R* __restrict__ alpha_out, R* __restrict__ beta_out,
+                   R* __restrict__ gamma_out, R* __restrict__ Bp_out) {
+    using MM = Mfma<R>;
+    constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D, NR = Sh::NR, NA = Sh::NA, LM = Sh::LM;
+    constexpr int DT = (D + M - 1) / M, DK = (D + KPI - 1) / KPI;
+    __shared__ R cbuf[M * M];
+    __shared__ R ebuf[M * D];
+    __shared__ R abuf[M * D];
+    const int T = dm.T, H = dm.H;
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, M, blockIdx.x, &a, &lo, &hi);
+    if (a < 0) return;
+    const int lane = threadIdx.x, j = lane % M, kk = lane / M;
+    const long ia = (lo + j < hi) ? long(order[lo + j]) : -1;
+    const R eb = ia >= 0 ? R(ebar_s[atom_struct[ia]]) : R(0);
     const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
     const R* __restrict__ w1 = W0 + (long)H * D + H;
-    for (int mu = 0; mu < H; ++mu) {
-        R da = R(0);
+    R dk[DK];
 #pragma unroll
-        for (int d = 0; d < D; ++d) da += W0[(long)mu * D + d] * dqs[d];
-        const R t = t_in[(long)i * H + mu];
-        const R sp = R(1) - t * t;
-        const R w = w1[mu];
-        alpha_out[(long)i * H + mu] = w * sp * (eb - R(2) * t * da);
-        beta_out[(long)i * H + mu] = w * sp;
-        gamma_out[(long)i * H + mu] = eb * t + sp * da;
-        const R c = R(-2) * w * t * sp * da;
-#pragma unroll
-        for (int d = 0; d < D; ++d) z[d] += c * W0[(long)mu * D + d];
+    for (int s = 0; s < DK; ++s) {
+        const int k = s * KPI + kk;
+        dk[s] = (ia >= 0 && k < D) ? qscale[k] * dq_in[ia * D + k] : R(0);
     }
-    R ab[D], e[D];
+    typename MM::Acc zacc[DT];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        e[d] = e_in[(long)i * D + d];
-        ab[d] = eb * e[d] + z[d] * qscale[d];
-        abar_out[(long)i * D + d] = ab[d];
+    for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) zacc[dt][v] = R(0);
+    for (int mu0 = 0; mu0 < H; mu0 += M) {
+        typename MM::Acc acc;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = R(0);
+        const int mrow = mu0 + j;
+#pragma unroll
+        for (int s = 0; s < DK; ++s) {
+            const int k = s * KPI + kk;
+            const R x = (mrow < H && k < D) ? W0[(long)mrow * D + k] : R(0);
+            acc = MM::mma(x, dk[s], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int r = MM::c_row(lane, v), mu = mu0 + r;
+            R c2 = R(0);
+            if (mu < H && ia >= 0) {
+                const R t = t_in[ia * H + mu], sp = R(1) - t * t, w = w1[mu], da = acc[v];
+                alpha_out[ia * H + mu] = w * sp * (eb - R(2) * t * da);
+                beta_out[ia * H + mu] = w * sp;
+                gamma_out[ia * H + mu] = eb * t + sp * da;
+                c2 = R(-2) * w * t * sp * da;
+            }
+            cbuf[r * M + j] = c2;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int dt = 0; dt < DT; ++dt) {
+            const int nu = dt * M + j;
+#pragma unroll
+            for (int s = 0; s < M / KPI; ++s) {
+                const int k = s * KPI + kk;
+                const R x = (nu < D && mu0 + k < H) ? W0[(long)(mu0 + k) * D + nu] : R(0);
+                zacc[dt] = MM::mma(x, cbuf[k * M + j], zacc[dt]);
+            }
+        }
+        __syncthreads();
     }
 #pragma unroll
-    for (int n = 0; n < NA; ++n) {
+    for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int nu = dt * M + MM::c_row(lane, v);
+            if (nu < D) {
+                const R ev = ia >= 0 ? e_in[ia * D + nu] : R(0);
+                const R ab = eb * ev + qscale[nu] * zacc[dt][v];
+                ebuf[j * D + nu] = ev;
+                abuf[j * D + nu] = ab;
+                if (ia >= 0) abar_out[ia * D + nu] = ab;
+            }
+        }
+    __syncthreads();
+    if (ia < 0) return;
+    const R* e = ebuf + j * D;
+    const R* ab = abuf + j * D;
+    constexpr int nsub = 64 / M;
+    for (int n = kk; n < NA; n += nsub) {
         R An[LM], dAn[LM], Bn[LM];
 #pragma unroll
         for (int lm = 0; lm < LM; ++lm) {
-            An[lm] = A_in[((long)i * NA + n) * LM + lm];
-            dAn[lm] = dA_in[((long)i * NA + n) * LM + lm];
+            An[lm] = A_in[(ia * NA + n) * LM + lm];
+            dAn[lm] = dA_in[(ia * NA + n) * LM + lm];
         }
 #pragma unroll
         for (int lm = 0; lm < LM; ++lm) {
@@ -537,183 +1035,7 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
                 Bn[m] += ab[idx] * R(4) * P * An[m] + e[idx] * (R(8) * dd * An[m] + R(4) * P * dAn[m]);
         }
 #pragma unroll
-        for (int lm = 0; lm < LM; ++lm) Bp_out[((long)i * NA + n) * LM + lm] = Bn[lm];
-    }
-}
-
-// -------------------------------------------------- angular coefficient grad
-
-// dL/dc_A[a][b][n][k] = sum_{i in a} sum_{j in b, angular}
-//     [ f_k (sum_lm Bp_nlm Y_lm + Q_nlm v.dY_lm) + f_k' (v.r^) sum_lm Q_nlm Y_lm ],
-// Q = B = dE_i/dA. Per-block partial rows (double) over a grid-stride loop.
-// Each team's per-segment sums go to its own LDS slot and are then added into
-// the block accumulator in team order, so the result is bitwise repeatable.
-template <typename R, class Sh, int S>
-__global__ void __launch_bounds__(kBlock)
-k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
-                     const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-                     const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ Bp_in,
-                     const R* __restrict__ Q_in, double* __restrict__ partial) {
-    constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM;
-    constexpr int NK = NA * KA, TEAMS = kBlock / S;
-    extern __shared__ unsigned char smem_raw[];
-    R* G = reinterpret_cast<R*>(smem_raw);
-    const int T = dm.T;
-    const int G_len = T * T * NK;
-    R* slot = G + G_len;                   // [TEAMS][NK]
-    int* team_type = reinterpret_cast<int*>(slot + TEAMS * NK);  // [TEAMS]
-    for (int x = threadIdx.x; x < G_len; x += kBlock) G[x] = R(0);
-    __syncthreads();
-    const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const R rcA = R(dm.rcA), irA = R(1.0 / dm.rcA);
-    const int tiles = (Na + kBlock / S - 1) / (kBlock / S);
-    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const int i = tile * (kBlock / S) + team;
-        const bool live = i < Na;
-        const int a = live ? types[i] : 0;
-        const int s = live ? atom_struct[i] : 0;
-        int64_t p = live ? row[i] : 0;
-        R ui[3], U[9];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) ui[d] = live ? ubar[(long)i * 3 + d] : R(0);
-#pragma unroll
-        for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
-        const R* __restrict__ Bpi = Bp_in + (long)i * NA * LM;
-        const R* __restrict__ Qi = Q_in + (long)i * NA * LM;
-        for (int b = 0; b < T; ++b) {
-            const int tot = live ? seg[(i * T + b) * 2] : 0;
-            const int ang = live ? seg[(i * T + b) * 2 + 1] : 0;
-            R acc[NA][KA];
-#pragma unroll
-            for (int n = 0; n < NA; ++n)
-#pragma unroll
-                for (int kk = 0; kk < KA; ++kk) acc[n][kk] = R(0);
-            for (int k = lane; k < ang; k += S) {
-                const Rec<R> pr = pairs[p + k];
-                const int j = rec_j(pr);
-                const R rv[3] = {pr.x, pr.y, pr.z};
-                R v[3];
-#pragma unroll
-                for (int be = 0; be < 3; ++be)
-                    v[be] = ui[be] - ubar[(long)j * 3 + be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
-                const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
-                const R ir = R(1) / r;
-                const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
-                const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
-                R fa[KA], fap[KA];
-                cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
-                const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
-                D1<R> Yd[LM];
-                solid_harmonics<D1<R>, R, Sh::L>(dx, dy, dz, Yd);
-                R Y[LM], vdY[LM];
-#pragma unroll
-                for (int lm = 0; lm < LM; ++lm) {
-                    Y[lm] = Yd[lm].v;
-                    vdY[lm] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
-                }
-#pragma unroll
-                for (int n = 0; n < NA; ++n) {
-                    R P = R(0), Rn = R(0);
-#pragma unroll
-                    for (int lm = 0; lm < LM; ++lm) {
-                        const R q = Qi[n * LM + lm];
-                        P += Bpi[n * LM + lm] * Y[lm] + q * vdY[lm];
-                        Rn += q * Y[lm];
-                    }
-                    Rn *= vu;
-#pragma unroll
-                    for (int kk = 0; kk < KA; ++kk) acc[n][kk] += P * fa[kk] + Rn * fap[kk];
-                }
-            }
-            p += tot;
-#pragma unroll
-            for (int n = 0; n < NA; ++n)
-#pragma unroll
-                for (int kk = 0; kk < KA; ++kk) {
-                    const R vsum = team_sum<S>(acc[n][kk]);
-                    if ((n * KA + kk) % S == lane) slot[team * NK + n * KA + kk] = live ? vsum : R(0);
-                }
-            if (lane == 0) team_type[team] = a;
-            __syncthreads();
-            for (int x = threadIdx.x; x < NK; x += kBlock)
-                for (int tm = 0; tm < TEAMS; ++tm) G[(team_type[tm] * T + b) * NK + x] += slot[tm * NK + x];
-            __syncthreads();
-        }
-    }
-    __syncthreads();
-    for (int x = threadIdx.x; x < G_len; x += kBlock) partial[(long)blockIdx.x * G_len + x] = double(G[x]);
-}
-
-// ------------------------------------------ network and radial coefficient grad
-
-// Partial rows over chunks of the species-sorted atom list. Row layout:
-// [0, offA): c_R[a][b][n][k] -> sum_i abar_n S0[b][k] + e_n S1[b][k];
-// [offA, offA + T (D+2) H): per species W0 -> alpha (x) s.q + beta (x) s.dq,
-// b0 -> -alpha, w1 -> gamma.
-template <typename R, class Sh>
-__global__ void __launch_bounds__(kBlock)
-k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict__ types,
-             const int* __restrict__ order, int Na, int chunk, const R* __restrict__ q_in,
-             const R* __restrict__ dq_in, const R* __restrict__ abar, const R* __restrict__ e_in,
-             const R* __restrict__ alpha, const R* __restrict__ beta, const R* __restrict__ gam,
-             const R* __restrict__ S0, const R* __restrict__ S1, double* __restrict__ partial) {
-    constexpr int NR = Sh::NR, KR = Sh::KR, D = Sh::D;
-    const int T = dm.T, H = dm.H;
-    const long nR = dm.offA;
-    const long rowlen = nR + (long)T * (D + 2) * H;
-    const int nchunks = (Na + chunk - 1) / chunk;
-    for (long col = threadIdx.x; col < rowlen; col += kBlock) {
-        // decode the column
-        int kind, a, x0, x1, x2;
-        if (col < nR) {
-            kind = 0;
-            long c = col;
-            x2 = int(c % KR);
-            c /= KR;
-            x1 = int(c % NR);
-            c /= NR;
-            x0 = int(c % T);
-            a = int(c / T);
-        } else {
-            long c = col - nR;
-            a = int(c / ((long)(D + 2) * H));
-            c %= (long)(D + 2) * H;
-            if (c < (long)H * D) {
-                kind = 1;
-                x0 = int(c / D);
-                x1 = int(c % D);
-            } else if (c < (long)H * D + H) {
-                kind = 2;
-                x0 = int(c - (long)H * D);
-            } else {
-                kind = 3;
-                x0 = int(c - (long)H * D - H);
-            }
-            x2 = 0;
-        }
-        double acc = 0.0;
-        for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-            const int lo = ch * chunk, hi = min(Na, lo + chunk);
-            R part = R(0);
-            for (int ii = lo; ii < hi; ++ii) {
-                const int i = order[ii];
-                if (types[i] != a) continue;
-                if (kind == 0) {
-                    part += abar[(long)i * D + x1] * S0[((long)i * T + x0) * KR + x2] +
-                            e_in[(long)i * D + x1] * S1[((long)i * T + x0) * KR + x2];
-                } else if (kind == 1) {
-                    const R s = qscale[x1];
-                    part += alpha[(long)i * H + x0] * s * q_in[(long)i * D + x1] +
-                            beta[(long)i * H + x0] * s * dq_in[(long)i * D + x1];
-                } else if (kind == 2) {
-                    part -= alpha[(long)i * H + x0];
-                } else {
-                    part += gam[(long)i * H + x0];
-                }
-            }
-            acc += double(part);
-        }
-        partial[(long)blockIdx.x * rowlen + col] = acc;
+        for (int lm = 0; lm < LM; ++lm) Bp_out[(ia * NA + n) * LM + lm] = Bn[lm];
     }
 }
 

@@ -139,6 +139,34 @@ k_neighbors(int Ns, long Na, int T, const int64_t* __restrict__ off, const R* __
     }
 }
 
+// reverse[p] = index of the pair (j, i, -n) for pair p = (i, j, n): the entry
+// of row j with neighbour i whose vector is closest to -r_ij (exactly -r_ij up
+// to rounding; other images of the same atom differ by a lattice vector).
+// -1 if the reverse pair was not kept (possible only at |r_ij| = rc to rounding).
+template <typename R>
+__global__ void __launch_bounds__(kNbBlock)
+k_reverse(long Na, const int64_t* __restrict__ row, const Rec<R>* __restrict__ pairs, int* __restrict__ reverse) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i >= Na) return;
+    for (int64_t p = row[i]; p < row[i + 1]; ++p) {
+        const Rec<R> a = pairs[p];
+        const long j = rec_j(a);
+        int64_t best = -1;
+        double bd = 1e300;
+        for (int64_t q = row[j]; q < row[j + 1]; ++q) {
+            const Rec<R> b = pairs[q];
+            if (rec_j(b) != i) continue;
+            const double dx = double(a.x) + double(b.x), dy = double(a.y) + double(b.y), dz = double(a.z) + double(b.z);
+            const double d = dx * dx + dy * dy + dz * dz;
+            if (d < bd) {
+                bd = d;
+                best = q;
+            }
+        }
+        reverse[p] = (best >= 0 && bd < 1e-6) ? int(best) : -1;
+    }
+}
+
 // Exclusive scan row[0..Na] of the per-row counts in row[1..Na] (row[0] = 0),
 // one block; also sums the angular counts into totals[1] (totals[0] = pairs).
 constexpr int kScanBlock = 1024;
@@ -253,6 +281,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     NEP_HIP(hipStreamSynchronize(st));
     nb->num_pairs = host_tot[0];
     nb->num_angular_pairs = host_tot[1];
+    if (host_tot[0] >= (int64_t(1) << 31)) return fail(NEP_ERR_UNSUPPORTED, "more than 2^31-1 pairs in one batch");
     if (host_tot[0] > nb->capacity) {
         return fail(NEP_ERR_CAPACITY, "neighbour capacity too small: need %lld pairs, have %lld",
                     (long long)host_tot[0], (long long)nb->capacity);
@@ -261,6 +290,8 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
         NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(grid), dim3(kNbBlock), 0, st, Ns, Na, T,
                    b->atom_offset, pos, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->seg_count, nb->row_offset,
                    nb->atom_struct, static_cast<Rec<R>*>(nb->pairs));
+        NEP_LAUNCH("neighbors_reverse", (k_reverse<R>), dim3(grid), dim3(kNbBlock), 0, st, Na, nb->row_offset,
+                   static_cast<const Rec<R>*>(nb->pairs), nb->reverse);
     }
     return NEP_OK;
 }

@@ -15,7 +15,7 @@ namespace nep {
 
 template <typename R, class Sh>
 nep_status run_shape(const Ctx& c) {
-    const Layout L = make_layout(c.dm, c.f64, c.Ns, c.Na);
+    const Layout L = make_layout(c.dm, c.f64, c.Ns, c.Na, c.pairs);
     if (c.ws_bytes < L.total) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, %zu needed", c.ws_bytes, L.total);
     auto Wr = [&](size_t off) { return reinterpret_cast<R*>(c.ws + off); };
     auto Wd = [&](size_t off) { return reinterpret_cast<double*>(c.ws + off); };
@@ -35,9 +35,10 @@ nep_status run_shape(const Ctx& c) {
                    Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0));
     if (c.mode == Mode::Descriptors) return NEP_OK;
 
+    const int net_grid = int((c.Na + Mfma<R>::M - 1) / Mfma<R>::M) + dm.T;
     if (Na > 0)
-        NEP_LAUNCH("network_forward", (k_network_forward<R, Sh>), dim3(atom_grid), dim3(kBlock), 0, st, dm, theta,
-                   qscale, c.types, Na, q, Wr(L.A), Wr(L.Eat), Wr(L.e), Wr(L.t), Wr(L.B), Wr(L.eps));
+        NEP_LAUNCH("network_forward", (k_network_forward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta, qscale,
+                   c.species_order, c.species_offset, q, Wr(L.A), Wr(L.Eat), Wr(L.e), Wr(L.t), Wr(L.B), Wr(L.eps));
 
     double* Es = c.E_out ? c.E_out : Wd(L.Es);
     double* Ws = c.W_out ? c.W_out : Wd(L.Ws);
@@ -47,7 +48,11 @@ nep_status run_shape(const Ctx& c) {
     if (c.mode == Mode::Forward || loss) {
         if (Na > 0)
             NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types, Na,
-                       c.row, c.seg, pairs, Wr(L.B), Wr(L.eps), F, Wr(L.Wat));
+                       c.row, c.seg, pairs, c.reverse, Wr(L.B), Wr(L.eps), reinterpret_cast<Rec<R>*>(Wr(L.h)),
+                       Wr(L.Fown), Wr(L.Wat));
+        if (Na > 0)
+            NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid), dim3(kBlock), 0, st, Na, c.row,
+                       c.reverse, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
         if (c.Ns > 0)
             NEP_LAUNCH("structure", (k_structure<R>), dim3(c.Ns), dim3(kRedBlock), 0, st, c.Ns, c.Na, c.atom_offset,
                        Wr(L.Eat), Wr(L.Wat), F, loss ? 1 : 0, c.Et, static_cast<const R*>(c.Ft), c.Wt, c.has_v,
@@ -64,21 +69,27 @@ nep_status run_shape(const Ctx& c) {
         NEP_LAUNCH("tangent", (k_tangent<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types,
                    c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dq), Wr(L.dA),
                    Wr(L.S1));
-        NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(atom_grid), dim3(kBlock), 0, st, dm, theta,
-                   qscale, c.types, c.atom_struct, Na, Wd(L.ebar), q, Wr(L.dq), Wr(L.e), Wr(L.t), Wr(L.A), Wr(L.dA),
-                   Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.Bp));
-        const size_t shm = sizeof(R) * (size_t(dm.T) * dm.T + kBlock / S) * Sh::NA * Sh::KA + sizeof(int) * (kBlock / S);
+        NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
+                   qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e), Wr(L.t),
+                   Wr(L.A), Wr(L.dA), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.Bp));
+        using CG = CoeffGradSmem<R, Sh, S>;
+        const size_t shm = CG::bytes(dm.T);
+        if (shm > 64 * 1024)
+            NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad<R, Sh, S>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
         NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad<R, Sh, S>), dim3(L.ang_rows), dim3(kBlock), shm, st,
                    dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.Bp), Wr(L.B),
                    Wd(L.ang_part));
-        NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), 0, st, dm, qscale, c.types,
-                   c.species_order, Na, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha), Wr(L.beta),
-                   Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));
+        NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), 0, st, dm, qscale,
+                   c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha),
+                   Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));
     }
-    const int pgrid = int((dm.P + kRedBlock - 1) / kRedBlock);
-    NEP_LAUNCH("final_reduce", (k_final_reduce<R>), dim3(pgrid), dim3(kRedBlock), 0, st, dm, c.Ns, c.atom_offset,
-               Wd(L.outer_part), Na > 0 ? L.outer_rows : 0, Wd(L.ang_part), Na > 0 ? L.ang_rows : 0, Wd(L.ebar),
-               Wd(L.lossp), c.lam_e, c.lam_f, c.lam_v, static_cast<R*>(c.grad), loss ? c.loss : nullptr);
+    if (Na > 0 && dm.offB1 > 0)
+        NEP_LAUNCH("reduce_stage", k_reduce_stage<kRedBlock / 64>, dim3(int((dm.offB1 + 63) / 64), kStageGroups), dim3(kRedBlock), 0,
+                   st, dm, Sh::NR * Sh::KR, Wd(L.outer_part), L.outer_rows, Wd(L.ang_part), L.ang_rows, Wd(L.stage));
+    NEP_LAUNCH("final_reduce", (k_final_reduce<R>), dim3(int((dm.offB1 + kRedBlock) / kRedBlock)), dim3(kRedBlock), 0,
+               st, dm, c.Ns, c.atom_offset, Wd(L.stage), Na > 0 ? kStageGroups : 0, Wd(L.ebar), Wd(L.lossp), c.lam_e,
+               c.lam_f, c.lam_v, static_cast<R*>(c.grad), loss ? c.loss : nullptr);
     return NEP_OK;
 }
 

@@ -47,13 +47,14 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
     for (int c = 0; c < 11; ++c) acc[c] = 0.0;
     const double cf = 2.0 * lam_f / (3.0 * double(Na));
     for (long i = a0 + threadIdx.x; i < a1; i += kRedBlock) {
+        const R fi[3] = {F[i * 3], F[i * 3 + 1], F[i * 3 + 2]};
         acc[0] += double(E_at[i]);
 #pragma unroll
         for (int c = 0; c < 9; ++c) acc[1 + c] += double(W_at[i * 9 + c]);
         if (loss) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const double r = double(F[i * 3 + d]) - double(Ft[i * 3 + d]);
+                const double r = double(fi[d]) - double(Ft[i * 3 + d]);
                 acc[10] += r * r;
                 ubar[i * 3 + d] = R(cf * r);
             }
@@ -113,38 +114,87 @@ k_seeds(int Ns, long Na, const double* __restrict__ dE, const R* __restrict__ dF
     if (t < 3 * Na) ubar[t] = dF ? dF[t] : R(0);
 }
 
-// grad[p] = fixed-order double sum of the partial rows that hold column p;
-// b1 gets -sum_s N_a^s ebar_s. Block 0 also writes loss[4].
+// Gradient reduction, stage 1: block (x, g) sums, for 64 consecutive
+// parameters (one per lane, coalesced), the partial rows r = 4 g + w,
+// 4 g + w + 4 G, ... (w = wave) and adds the four wave sums in wave order into
+// stage[g][p]. Network and radial-coefficient columns come from the
+// species-tagged rows of the outer reduction, angular coefficients from the
+// angular rows.
+constexpr int kStageGroups = 16;
+
+template <int WAVES_PER_BLOCK>
+__global__ void __launch_bounds__(kRedBlock)
+k_reduce_stage(Dims dm, int NRKR, const double* __restrict__ outer_part, int outer_rows,
+               const double* __restrict__ ang_part, int ang_rows, double* __restrict__ stage) {
+    __shared__ double red[kRedBlock];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = WAVES_PER_BLOCK;
+    const int g = blockIdx.y, G = gridDim.y;
+    const long p = (long)blockIdx.x * 64 + lane;
+    const int T = dm.T, H = dm.H, D = dm.D;
+    const long net_w = long(D + 2) * H;
+    const long W1 = net_w + long(T) * NRKR;
+    double s = 0.0;
+    if (p < dm.offB1) {
+        long col = -1;
+        int a = 0;
+        if (p < dm.offA) {
+            a = int(p / (long(T) * NRKR));
+            col = net_w + p % (long(T) * NRKR);
+        } else if (p >= dm.offN) {
+            a = int((p - dm.offN) / net_w);
+            col = (p - dm.offN) % net_w;
+        }
+        const int step = waves * G;
+        if (col >= 0) {
+            for (int r = g * waves + wave; r < outer_rows; r += step) {
+                const double* row = outer_part + (long)r * (W1 + 1);
+                if (row[0] == double(a)) s += row[1 + col];
+            }
+        } else {
+            const long angw = dm.offN - dm.offA;
+            for (int r = g * waves + wave; r < ang_rows; r += step) s += ang_part[(long)r * angw + (p - dm.offA)];
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (wave == 0 && p < dm.offB1) {
+        double t = 0.0;
+        for (int w = 0; w < waves; ++w) t += red[w * 64 + lane];
+        stage[(long)g * dm.offB1 + p] = t;
+    }
+}
+
+// Stage 2: grad[p] = sum over groups in order; b1 gets -sum_s N_a^s ebar_s;
+// block 0 also writes loss[4] = {L, Delta_E, Delta_F, Delta_V}.
 template <typename R>
 __global__ void __launch_bounds__(kRedBlock)
-k_final_reduce(Dims dm, int Ns, const int64_t* __restrict__ off, const double* __restrict__ outer_part,
-               int outer_rows, const double* __restrict__ ang_part, int ang_rows, const double* __restrict__ ebar,
-               const double* __restrict__ lossp, double lam_e, double lam_f, double lam_v, R* __restrict__ grad,
-               double* __restrict__ loss) {
+k_final_reduce(Dims dm, int Ns, const int64_t* __restrict__ off, const double* __restrict__ stage, int G,
+               const double* __restrict__ ebar, const double* __restrict__ lossp, double lam_e, double lam_f,
+               double lam_v, R* __restrict__ grad, double* __restrict__ loss) {
+    __shared__ double scratch[kRedBlock / 64];
     const long p = (long)blockIdx.x * kRedBlock + threadIdx.x;
-    const long rowlen = dm.offA + (dm.offB1 - dm.offN);
-    const long angw = dm.offN - dm.offA;
-    if (p < dm.P) {
-        double s = 0.0;
-        if (p < dm.offA) {
-            for (int r = 0; r < outer_rows; ++r) s += outer_part[(long)r * rowlen + p];
-        } else if (p < dm.offN) {
-            for (int r = 0; r < ang_rows; ++r) s += ang_part[(long)r * angw + (p - dm.offA)];
-        } else if (p < dm.offB1) {
-            const long c = dm.offA + (p - dm.offN);
-            for (int r = 0; r < outer_rows; ++r) s += outer_part[(long)r * rowlen + c];
-        } else {
-            for (int t = 0; t < Ns; ++t) s -= double(off[t + 1] - off[t]) * ebar[t];
-        }
-        grad[p] = R(s);
+    if (p < dm.offB1) {
+        double t = 0.0;
+        for (int g = 0; g < G; ++g) t += stage[(long)g * dm.offB1 + p];
+        grad[p] = R(t);
     }
-    if (loss && blockIdx.x == 0 && threadIdx.x == 0) {
-        double dE = 0.0, dF = 0.0, dV = 0.0;
-        for (int t = 0; t < Ns; ++t) {
+    if (blockIdx.x != 0) return;
+    double sb = 0.0, dE = 0.0, dF = 0.0, dV = 0.0;
+    for (int t = threadIdx.x; t < Ns; t += kRedBlock) {
+        sb -= double(off[t + 1] - off[t]) * ebar[t];
+        if (loss) {
             dE += lossp[t * 3 + 0];
             dF += lossp[t * 3 + 1];
             dV += lossp[t * 3 + 2];
         }
+    }
+    sb = block_sum(sb, scratch);
+    if (threadIdx.x == 0) grad[dm.offB1] = R(sb);
+    if (!loss) return;
+    dE = block_sum(dE, scratch);
+    dF = block_sum(dF, scratch);
+    dV = block_sum(dV, scratch);
+    if (threadIdx.x == 0) {
         loss[0] = lam_e * dE + lam_f * dF + lam_v * dV;
         loss[1] = dE;
         loss[2] = dF;

@@ -45,7 +45,8 @@ class c_batch(C.Structure):
 
 class c_neighbors(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("row_offset", C.c_void_p), ("seg_count", C.c_void_p),
-                ("pairs", C.c_void_p), ("atom_struct", C.c_void_p), ("species_order", C.c_void_p),
+                ("pairs", C.c_void_p), ("reverse", C.c_void_p), ("atom_struct", C.c_void_p),
+                ("species_order", C.c_void_p),
                 ("species_offset", C.c_void_p), ("num_pairs", C.c_int64), ("num_angular_pairs", C.c_int64)]
 
 
@@ -179,6 +180,7 @@ class Neighbors:
         self.row_offset = torch.zeros(Na + 1, dtype=torch.int64, device=dev)
         self.seg_count = torch.zeros((Na, T, 2), dtype=torch.int32, device=dev)
         self.pairs = torch.zeros((max(capacity, 1), 4), dtype=model.torch_dtype, device=dev)
+        self.reverse = torch.zeros(max(capacity, 1), dtype=torch.int32, device=dev)
         self.atom_struct = torch.zeros(max(Na, 1), dtype=torch.int32, device=dev)
         self.species_order = torch.zeros(max(Na, 1), dtype=torch.int32, device=dev)
         self.species_offset = torch.zeros(T + 1, dtype=torch.int64, device=dev)
@@ -188,7 +190,8 @@ class Neighbors:
 
     def c(self) -> c_neighbors:
         return c_neighbors(self.capacity, _ptr(self.row_offset), _ptr(self.seg_count), _ptr(self.pairs),
-                           _ptr(self.atom_struct), _ptr(self.species_order), _ptr(self.species_offset),
+                           _ptr(self.reverse), _ptr(self.atom_struct), _ptr(self.species_order),
+                           _ptr(self.species_offset),
                            self.num_pairs, self.num_angular_pairs)
 
     def neighbor_index(self):

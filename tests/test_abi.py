@@ -86,7 +86,7 @@ def test_calls_validate_before_launching():
     rc = L.nep_forward(C.byref(m), None, None, None, None, None, None, None, None, None, 0, None)
     assert rc == nep.NEP_ERR_INVALID_ARG and L.nep_last_error()
     batch = nep.c_batch(1, 4, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8))
-    nb = nep.c_neighbors(0, *([C.c_void_p(8)] * 6), 0, 0)
+    nb = nep.c_neighbors(0, *([C.c_void_p(8)] * 7), 0, 0)
     odd = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=5, n_max_a=4, basis_r=8, basis_a=8, hidden=30).c()
     rc = L.nep_forward(C.byref(odd), C.c_void_p(8), C.c_void_p(8), C.byref(batch), C.byref(nb), C.c_void_p(8),
                        None, None, None, C.c_void_p(8), 1 << 20, None)
