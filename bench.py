@@ -45,6 +45,9 @@ def parse():
     p.add_argument("--no-comparator", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-structures", type=int, default=256)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="also run one device-to-device copy of this many MiB (a known-size kernel that "
+                        "calibrates hardware byte counters)")
     return p.parse_args()
 
 
@@ -167,6 +170,16 @@ def main():
     ms = start.elapsed_time(stop) / args.steps
     sps = host.num_structures / (ms * 1e-3)
     log(f"timed {args.steps} steps: {ms:.4f} ms/step, {sps:.1f} structures/s, loss {loss[0].item():.6e}")
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read and written once")
+        del src, dst
 
     # per-kernel event timing on the launch stream
     N.nep_profile_enable(True)

@@ -123,8 +123,6 @@ Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs) {
     L.Eat = take(r * na);
     L.e = take(r * na * dm.D);
     L.t = take(r * na * dm.H);
-    L.B = take(r * na * dm.NA * dm.LM);
-    L.eps = take(r * na * dm.T * dm.KR);
     L.F = take(r * na * 3);
     L.Fown = take(r * na * 3);
     L.h = take(4 * r * size_t(pairs > 0 ? pairs : 0));
@@ -136,7 +134,6 @@ Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs) {
     L.alpha = take(r * na * dm.H);
     L.beta = take(r * na * dm.H);
     L.gam = take(r * na * dm.H);
-    L.Bp = take(r * na * dm.NA * dm.LM);
     L.Es = take(8 * ns);
     L.Ws = take(8 * ns * 9);
     L.ebar = take(8 * ns);

@@ -89,7 +89,7 @@ struct Ctx {
 
 // Workspace carve-up (byte offsets), identical for every shape of given sizes.
 struct Layout {
-    size_t q, A, S0, S1, Eat, e, t, B, eps, F, Fown, Wat, ubar, dq, dA, abar, alpha, beta, gam, Bp, h;
+    size_t q, A, S0, S1, Eat, e, t, F, Fown, Wat, ubar, dq, dA, abar, alpha, beta, gam, h;
     size_t Es, Ws, ebar, Ubar, lossp, outer_part, ang_part, stage, nbr_totals;
     size_t total;
     int outer_rows, ang_rows, outer_chunk;

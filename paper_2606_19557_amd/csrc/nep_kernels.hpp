@@ -161,6 +161,62 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
     }
 }
 
+// ------------------------------------------------ per-atom moment adjoints
+
+// B = dE_i/dA[n][lm] (Eq. 20 and the 4/5-body terms, with e = dE_i/dq) and,
+// when WITH_BP, Bp = dPsi/dA[n][lm] for Psi = abar . q + e . dq (abar = dPsi/dq,
+// dA the tangent of the moments). The S lanes of a team take entries
+// x = lane, lane + S, ... of the atom's NA x LM block.
+template <typename R, class Sh, int S, bool WITH_BP>
+__device__ __forceinline__ void moment_adjoints(int lane, const R* __restrict__ A, const R* __restrict__ dA,
+                                                const R* __restrict__ e, const R* __restrict__ ab, R* B, R* Bp) {
+    constexpr int NR = Sh::NR, NA = Sh::NA, LM = Sh::LM, L = Sh::L;
+    for (int x = lane; x < NA * LM; x += S) {
+        const int n = x / LM, lm = x % LM;
+        const int l = lm < 3 ? 1 : lm < 8 ? 2 : lm < 15 ? 3 : 4;
+        const int idx = NR + (l - 1) * NA + n;
+        const R a = A[x];
+        R b = R(2) * e[idx] * a;
+        R bp = R(0);
+        if (WITH_BP) bp = R(2) * ab[idx] * a + R(2) * e[idx] * dA[x];
+        if (Sh::H4 && l == 2) {
+            R a2[5], g4[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) a2[m] = A[n * LM + 3 + m];
+            q4_grad<R>(a2, g4);
+            R gm = g4[0];
+#pragma unroll
+            for (int m = 1; m < 5; ++m)
+                if (lm - 3 == m) gm = g4[m];
+            const int i4 = NR + L * NA + n;
+            b += e[i4] * gm;
+            if (WITH_BP) {
+                R d2[5], h4[5];
+#pragma unroll
+                for (int m = 0; m < 5; ++m) d2[m] = dA[n * LM + 3 + m];
+                q4_hess_vec<R>(a2, d2, h4);
+                R hm = h4[0];
+#pragma unroll
+                for (int m = 1; m < 5; ++m)
+                    if (lm - 3 == m) hm = h4[m];
+                bp += ab[i4] * gm + e[i4] * hm;
+            }
+        }
+        if (Sh::H5 && l == 1) {
+            const R a0 = A[n * LM], a1 = A[n * LM + 1], a2 = A[n * LM + 2];
+            const R P = a0 * a0 + a1 * a1 + a2 * a2;
+            const int i5 = NR + (L + (Sh::H4 ? 1 : 0)) * NA + n;
+            b += e[i5] * R(4) * P * a;
+            if (WITH_BP) {
+                const R dd = a0 * dA[n * LM] + a1 * dA[n * LM + 1] + a2 * dA[n * LM + 2];
+                bp += ab[i5] * R(4) * P * a + e[i5] * (R(8) * dd * a + R(4) * P * dA[x]);
+            }
+        }
+        B[x] = b;
+        if (WITH_BP) Bp[x] = bp;
+    }
+}
+
 // ------------------------------------------------------------------- force
 
 // h_ij = dE_i/dr_ij for every pair of atom i's row, from atom i's own
@@ -173,9 +229,9 @@ template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
 k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
         const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-        const int* __restrict__ reverse, const R* __restrict__ B_in, const R* __restrict__ eps_in,
+        const int* __restrict__ reverse, const R* __restrict__ A_in, const R* __restrict__ e_in,
         Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
-    constexpr int NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM;
+    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D;
     constexpr int TEAMS = kBlock / S;
     __shared__ R Bsh[TEAMS][NA * LM];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
@@ -185,7 +241,12 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
     const int a = live ? types[i] : 0;
     int64_t p = live ? row[i] : 0;
-    for (int x = lane; x < NA * LM; x += S) Bsh[team][x] = live ? B_in[(long)i * NA * LM + x] : R(0);
+    const R* __restrict__ ei = e_in + (long)(live ? i : 0) * D;
+    if (live) {
+        moment_adjoints<R, Sh, S, false>(lane, A_in + (long)i * NA * LM, nullptr, ei, nullptr, Bsh[team], nullptr);
+    } else {
+        for (int x = lane; x < NA * LM; x += S) Bsh[team][x] = R(0);
+    }
     __syncthreads();
     const R* Bk = Bsh[team];
     R F[3] = {R(0), R(0), R(0)};
@@ -195,9 +256,19 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
     for (int b = 0; b < T; ++b) {
         const int tot = live ? seg[(i * T + b) * 2] : 0;
         const int ang = live ? seg[(i * T + b) * 2 + 1] : 0;
+        // radial force coefficients eps_k = sum_n e_n c_R[a][b][n][k]
         R epsk[KR];
+        const R* __restrict__ cRab = theta + (long)((a * T + b) * NR) * KR;
 #pragma unroll
-        for (int kk = 0; kk < KR; ++kk) epsk[kk] = live ? eps_in[((long)i * T + b) * KR + kk] : R(0);
+        for (int kk = 0; kk < KR; ++kk) epsk[kk] = R(0);
+        if (live) {
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+                const R en = ei[n];
+#pragma unroll
+                for (int kk = 0; kk < KR; ++kk) epsk[kk] += en * cRab[n * KR + kk];
+            }
+        }
         const R* __restrict__ cA = theta + dm.offA + (long)((a * T + b) * NA) * KA;
         for (int k = lane; k < tot; k += S) {
             const Rec<R> pr = pairs[p + k];
@@ -504,9 +575,10 @@ template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
 k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
                      const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-                     const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ Bp_in,
-                     const R* __restrict__ Q_in, double* __restrict__ partial) {
-    constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L;
+                     const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ A_in,
+                     const R* __restrict__ dA_in, const R* __restrict__ e_in, const R* __restrict__ abar,
+                     double* __restrict__ partial) {
+    constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L, D = Sh::D;
     using X = MomentExchange<R, NA, KA, S>;
     constexpr int OWN = X::OWN, NK = NA * KA, TEAMS = kBlock / S;
     extern __shared__ unsigned char smem_raw[];
@@ -536,9 +608,11 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
 #pragma unroll
         for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
         __syncthreads();
-        for (int x = lane; x < NA * LM; x += S) {
-            myBp[x] = live ? Bp_in[(long)i * NA * LM + x] : R(0);
-            myQ[x] = live ? Q_in[(long)i * NA * LM + x] : R(0);
+        if (live) {
+            moment_adjoints<R, Sh, S, true>(lane, A_in + (long)i * NA * LM, dA_in + (long)i * NA * LM,
+                                            e_in + (long)i * D, abar + (long)i * D, myQ, myBp);
+        } else {
+            for (int x = lane; x < NA * LM; x += S) myBp[x] = myQ[x] = R(0);
         }
         __syncthreads();
         for (int b = 0; b < T; ++b) {
@@ -752,10 +826,23 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
         const int mu = mu0 + lane;
         R sa = R(0), sg = R(0);
         if (mu < H)
-            for (long s = lo + wave; s < hi; s += WAVES) {
-                const long i = order[s];
-                sa += alpha[i * H + mu];
-                sg += gam[i * H + mu];
+            for (long s0 = lo + wave; s0 < hi; s0 += 8 * WAVES) {
+                R xa[8], xg[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const long sidx = s0 + u * WAVES;
+                    xa[u] = xg[u] = R(0);
+                    if (sidx < hi) {
+                        const long i = order[sidx];
+                        xa[u] = alpha[i * H + mu];
+                        xg[u] = gam[i * H + mu];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    sa += xa[u];
+                    sg += xg[u];
+                }
             }
         __syncthreads();
         red[wave * 64 + lane] = sa;
@@ -781,48 +868,16 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
 // sit in the lanes that share its column. The second product of each pass
 // (W0^T times a per-hidden-unit factor) is fed through an LDS transpose.
 
-// dE_i/dA[n][lm] for the moments of atom row `ia` (lane share n = kk, kk + nsub, ...).
-template <typename R, class Sh>
-__device__ __forceinline__ void moments_adjoint(const R* e, const R* __restrict__ A_in, long ia, int kk, int nsub,
-                                                R* __restrict__ B_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, LM = Sh::LM;
-    for (int n = kk; n < NA; n += nsub) {
-        R An[LM], Bn[LM];
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) An[lm] = A_in[(ia * NA + n) * LM + lm];
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) Bn[lm] = R(2) * e[NR + (lm_degree<LM>(lm) - 1) * NA + n] * An[lm];
-        if (Sh::H4) {
-            R g4[5];
-            q4_grad<R>(&An[3], g4);
-            const R e4 = e[NR + Sh::L * NA + n];
-#pragma unroll
-            for (int m = 0; m < 5; ++m) Bn[3 + m] += e4 * g4[m];
-        }
-        if (Sh::H5) {
-            const R P = An[0] * An[0] + An[1] * An[1] + An[2] * An[2];
-            const R e5 = e[NR + (Sh::L + (Sh::H4 ? 1 : 0)) * NA + n];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) Bn[m] += e5 * R(4) * P * An[m];
-        }
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) B_out[(ia * NA + n) * LM + lm] = Bn[lm];
-    }
-}
-
-// E_i, e_i = dE_i/dq_i and tanh activations (Eqs. 2-3), then per atom
-// B = dE_i/dA[n][lm] and the radial force coefficients eps[b][k] = sum_n e_n c_R[a][b][n][k].
+// E_i, e_i = dE_i/dq_i and tanh activations (Eqs. 2-3).
 template <typename R, class Sh>
 __global__ void __launch_bounds__(64)
 k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
                   const int* __restrict__ order, const int64_t* __restrict__ soff, const R* __restrict__ q_in,
-                  const R* __restrict__ A_in, R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out,
-                  R* __restrict__ B_out, R* __restrict__ eps_out) {
+                  R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out) {
     using MM = Mfma<R>;
-    constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D, NR = Sh::NR, KR = Sh::KR;
+    constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D;
     constexpr int DT = (D + M - 1) / M, DK = (D + KPI - 1) / KPI;
     __shared__ R cbuf[M * M];
-    __shared__ R ebuf[M * D];
     const int T = dm.T, H = dm.H;
     int a;
     long lo = 0, hi = 0;
@@ -890,46 +945,25 @@ k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restric
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int nu = dt * M + MM::c_row(lane, v);
-            if (nu < D) {
-                const R val = qscale[nu] * eacc[dt][v];
-                ebuf[j * D + nu] = val;
-                if (ia >= 0) e_out[ia * D + nu] = val;
-            }
+            if (nu < D && ia >= 0) e_out[ia * D + nu] = qscale[nu] * eacc[dt][v];
         }
-    __syncthreads();
-    if (ia < 0) return;
-    const R* e = ebuf + j * D;
-    constexpr int nsub = 64 / M;
-    moments_adjoint<R, Sh>(e, A_in, ia, kk, nsub, B_out);
-    for (int bk = kk; bk < T * KR; bk += nsub) {
-        const int b = bk / KR, k = bk % KR;
-        const R* __restrict__ cR = theta + (long)((a * T + b) * NR) * KR + k;
-        R sum = R(0);
-#pragma unroll
-        for (int n = 0; n < NR; ++n) sum += e[n] * cR[n * KR];
-        eps_out[(ia * T + b) * KR + k] = sum;
-    }
 }
 
 // For Psi = sum_i ebar_s E_i + e(q_i) . dq_i (the force/virial adjoint): the
 // Hessian-vector product da = W0 (s dq), per-unit weight-gradient factors
-// alpha = w1 s'(ebar - 2 t da), beta = w1 s', gamma = ebar t + s' da,
-// abar = dPsi/dq = ebar e + s (W0^T (-2 w1 t s' da)), and per atom
-// Bp = dPsi/dA[n][lm].
+// alpha = w1 s'(ebar - 2 t da), beta = w1 s', gamma = ebar t + s' da, and
+// abar = dPsi/dq = ebar e + s (W0^T (-2 w1 t s' da)).
 template <typename R, class Sh>
 __global__ void __launch_bounds__(64)
 k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
                    const int* __restrict__ order, const int64_t* __restrict__ soff, const int* __restrict__ atom_struct,
                    const double* __restrict__ ebar_s, const R* __restrict__ dq_in, const R* __restrict__ e_in,
-                   const R* __restrict__ t_in, const R* __restrict__ A_in, const R* __restrict__ dA_in,
-                   R* __restrict__ abar_out, R* __restrict__ alpha_out, R* __restrict__ beta_out,
-                   R* __restrict__ gamma_out, R* __restrict__ Bp_out) {
+                   const R* __restrict__ t_in, R* __restrict__ abar_out, R* __restrict__ alpha_out,
+                   R* __restrict__ beta_out, R* __restrict__ gamma_out) {
     using MM = Mfma<R>;
-    constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D, NR = Sh::NR, NA = Sh::NA, LM = Sh::LM;
+    constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D;
     constexpr int DT = (D + M - 1) / M, DK = (D + KPI - 1) / KPI;
     __shared__ R cbuf[M * M];
-    __shared__ R ebuf[M * D];
-    __shared__ R abuf[M * D];
     const int T = dm.T, H = dm.H;
     int a;
     long lo = 0, hi = 0;
@@ -993,50 +1027,8 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int nu = dt * M + MM::c_row(lane, v);
-            if (nu < D) {
-                const R ev = ia >= 0 ? e_in[ia * D + nu] : R(0);
-                const R ab = eb * ev + qscale[nu] * zacc[dt][v];
-                ebuf[j * D + nu] = ev;
-                abuf[j * D + nu] = ab;
-                if (ia >= 0) abar_out[ia * D + nu] = ab;
-            }
+            if (nu < D && ia >= 0) abar_out[ia * D + nu] = eb * e_in[ia * D + nu] + qscale[nu] * zacc[dt][v];
         }
-    __syncthreads();
-    if (ia < 0) return;
-    const R* e = ebuf + j * D;
-    const R* ab = abuf + j * D;
-    constexpr int nsub = 64 / M;
-    for (int n = kk; n < NA; n += nsub) {
-        R An[LM], dAn[LM], Bn[LM];
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) {
-            An[lm] = A_in[(ia * NA + n) * LM + lm];
-            dAn[lm] = dA_in[(ia * NA + n) * LM + lm];
-        }
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) {
-            const int idx = NR + (lm_degree<LM>(lm) - 1) * NA + n;
-            Bn[lm] = R(2) * ab[idx] * An[lm] + R(2) * e[idx] * dAn[lm];
-        }
-        if (Sh::H4) {
-            R g4[5], h4[5];
-            q4_grad<R>(&An[3], g4);
-            q4_hess_vec<R>(&An[3], &dAn[3], h4);
-            const int idx = NR + Sh::L * NA + n;
-#pragma unroll
-            for (int m = 0; m < 5; ++m) Bn[3 + m] += ab[idx] * g4[m] + e[idx] * h4[m];
-        }
-        if (Sh::H5) {
-            const R P = An[0] * An[0] + An[1] * An[1] + An[2] * An[2];
-            const R dd = An[0] * dAn[0] + An[1] * dAn[1] + An[2] * dAn[2];
-            const int idx = NR + (Sh::L + (Sh::H4 ? 1 : 0)) * NA + n;
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-                Bn[m] += ab[idx] * R(4) * P * An[m] + e[idx] * (R(8) * dd * An[m] + R(4) * P * dAn[m]);
-        }
-#pragma unroll
-        for (int lm = 0; lm < LM; ++lm) Bp_out[(ia * NA + n) * LM + lm] = Bn[lm];
-    }
 }
 
 }  // namespace nep

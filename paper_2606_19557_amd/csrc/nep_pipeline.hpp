@@ -38,7 +38,7 @@ nep_status run_shape(const Ctx& c) {
     const int net_grid = int((c.Na + Mfma<R>::M - 1) / Mfma<R>::M) + dm.T;
     if (Na > 0)
         NEP_LAUNCH("network_forward", (k_network_forward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta, qscale,
-                   c.species_order, c.species_offset, q, Wr(L.A), Wr(L.Eat), Wr(L.e), Wr(L.t), Wr(L.B), Wr(L.eps));
+                   c.species_order, c.species_offset, q, Wr(L.Eat), Wr(L.e), Wr(L.t));
 
     double* Es = c.E_out ? c.E_out : Wd(L.Es);
     double* Ws = c.W_out ? c.W_out : Wd(L.Ws);
@@ -48,7 +48,7 @@ nep_status run_shape(const Ctx& c) {
     if (c.mode == Mode::Forward || loss) {
         if (Na > 0)
             NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types, Na,
-                       c.row, c.seg, pairs, c.reverse, Wr(L.B), Wr(L.eps), reinterpret_cast<Rec<R>*>(Wr(L.h)),
+                       c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e), reinterpret_cast<Rec<R>*>(Wr(L.h)),
                        Wr(L.Fown), Wr(L.Wat));
         if (Na > 0)
             NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid), dim3(kBlock), 0, st, Na, c.row,
@@ -71,15 +71,15 @@ nep_status run_shape(const Ctx& c) {
                    Wr(L.S1));
         NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
                    qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e), Wr(L.t),
-                   Wr(L.A), Wr(L.dA), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.Bp));
+                   Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
         using CG = CoeffGradSmem<R, Sh, S>;
         const size_t shm = CG::bytes(dm.T);
         if (shm > 64 * 1024)
             NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad<R, Sh, S>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
         NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad<R, Sh, S>), dim3(L.ang_rows), dim3(kBlock), shm, st,
-                   dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.Bp), Wr(L.B),
-                   Wd(L.ang_part));
+                   dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dA),
+                   Wr(L.e), Wr(L.abar), Wd(L.ang_part));
         NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), 0, st, dm, qscale,
                    c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha),
                    Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));
