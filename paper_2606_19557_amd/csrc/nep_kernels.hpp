@@ -791,7 +791,7 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
                 if (sa < hi) {
                     const long i = order[sa];
                     if (wtile) {
-                        if (rr < H) xs[u] = (sterm ? beta : alpha)[i * H + rr];
+                        if (rr < H) xs[u] = (sterm ? beta : alpha)[sa * H + rr];
                         if (cc < D) ys[u] = sc * (sterm ? dq_in : q_in)[i * D + cc];
                     } else {
                         if (rr < NR) xs[u] = (sterm ? e_in : abar)[i * D + rr];
@@ -833,9 +833,8 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
                     const long sidx = s0 + u * WAVES;
                     xa[u] = xg[u] = R(0);
                     if (sidx < hi) {
-                        const long i = order[sidx];
-                        xa[u] = alpha[i * H + mu];
-                        xg[u] = gam[i * H + mu];
+                        xa[u] = alpha[sidx * H + mu];
+                        xg[u] = gam[sidx * H + mu];
                     }
                 }
 #pragma unroll
@@ -868,6 +867,30 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
 // sit in the lanes that share its column. The second product of each pass
 // (W0^T times a per-hidden-unit factor) is fed through an LDS transpose.
 
+// Per-hidden-unit arrays (t, alpha, beta, gamma) are stored by position in the
+// species-sorted atom list, row s = H units. A block's M atoms are rows
+// lo .. lo + nat - 1, so its tile is one contiguous span: it moves through an
+// LDS tile [atom][unit] (padded to M + 1) with whole-line coalesced accesses.
+template <typename R, int M>
+__device__ __forceinline__ void store_unit_tile(const R* tile, R* __restrict__ out, long lo, int nat, int H,
+                                                int mu0, int lane) {
+    const int nrow = H - mu0 < M ? H - mu0 : M;
+    for (int x = lane; x < nat * nrow; x += 64) {
+        const int jj = x / nrow, r = x % nrow;
+        out[(lo + jj) * H + mu0 + r] = tile[jj * (M + 1) + r];
+    }
+}
+
+template <typename R, int M>
+__device__ __forceinline__ void load_unit_tile(const R* __restrict__ in, R* tile, long lo, int nat, int H, int mu0,
+                                               int lane) {
+    const int nrow = H - mu0 < M ? H - mu0 : M;
+    for (int x = lane; x < nat * nrow; x += 64) {
+        const int jj = x / nrow, r = x % nrow;
+        tile[jj * (M + 1) + r] = in[(lo + jj) * H + mu0 + r];
+    }
+}
+
 // E_i, e_i = dE_i/dq_i and tanh activations (Eqs. 2-3).
 template <typename R, class Sh>
 __global__ void __launch_bounds__(64)
@@ -878,6 +901,7 @@ k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restric
     constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D;
     constexpr int DT = (D + M - 1) / M, DK = (D + KPI - 1) / KPI;
     __shared__ R cbuf[M * M];
+    __shared__ R obuf[M * (M + 1)];
     const int T = dm.T, H = dm.H;
     int a;
     long lo = 0, hi = 0;
@@ -885,6 +909,7 @@ k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restric
     if (a < 0) return;
     const int lane = threadIdx.x, j = lane % M, kk = lane / M;
     const long ia = (lo + j < hi) ? long(order[lo + j]) : -1;
+    const int nat = int(hi - lo < M ? hi - lo : M);
     const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
     const R* __restrict__ b0 = W0 + (long)H * D;
     const R* __restrict__ w1 = b0 + H;
@@ -917,7 +942,7 @@ k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restric
             R c = R(0);
             if (mu < H) {
                 const R t = tanh_<R>(acc[v] - b0[mu]);
-                if (ia >= 0) t_out[ia * H + mu] = t;
+                obuf[j * (M + 1) + r] = t;
                 const R w = w1[mu];
                 Ej += w * t;
                 c = w * (R(1) - t * t);
@@ -925,6 +950,7 @@ k_network_forward(const Dims dm, const R* __restrict__ theta, const R* __restric
             cbuf[r * M + j] = c;
         }
         __syncthreads();
+        store_unit_tile<R, M>(obuf, t_out, lo, nat, H, mu0, lane);
 #pragma unroll
         for (int dt = 0; dt < DT; ++dt) {
             const int nu = dt * M + j;
@@ -964,6 +990,7 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
     constexpr int M = MM::M, KPI = MM::KPI, NV = MM::NV, D = Sh::D;
     constexpr int DT = (D + M - 1) / M, DK = (D + KPI - 1) / KPI;
     __shared__ R cbuf[M * M];
+    __shared__ R obuf[4][M * (M + 1)];
     const int T = dm.T, H = dm.H;
     int a;
     long lo = 0, hi = 0;
@@ -971,6 +998,7 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
     if (a < 0) return;
     const int lane = threadIdx.x, j = lane % M, kk = lane / M;
     const long ia = (lo + j < hi) ? long(order[lo + j]) : -1;
+    const int nat = int(hi - lo < M ? hi - lo : M);
     const R eb = ia >= 0 ? R(ebar_s[atom_struct[ia]]) : R(0);
     const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
     const R* __restrict__ w1 = W0 + (long)H * D + H;
@@ -986,6 +1014,7 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
 #pragma unroll
         for (int v = 0; v < NV; ++v) zacc[dt][v] = R(0);
     for (int mu0 = 0; mu0 < H; mu0 += M) {
+        load_unit_tile<R, M>(t_in, obuf[3], lo, nat, H, mu0, lane);
         typename MM::Acc acc;
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = R(0);
@@ -996,20 +1025,24 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
             const R x = (mrow < H && k < D) ? W0[(long)mrow * D + k] : R(0);
             acc = MM::mma(x, dk[s], acc);
         }
+        __syncthreads();
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int r = MM::c_row(lane, v), mu = mu0 + r;
             R c2 = R(0);
             if (mu < H && ia >= 0) {
-                const R t = t_in[ia * H + mu], sp = R(1) - t * t, w = w1[mu], da = acc[v];
-                alpha_out[ia * H + mu] = w * sp * (eb - R(2) * t * da);
-                beta_out[ia * H + mu] = w * sp;
-                gamma_out[ia * H + mu] = eb * t + sp * da;
+                const R t = obuf[3][j * (M + 1) + r], sp = R(1) - t * t, w = w1[mu], da = acc[v];
+                obuf[0][j * (M + 1) + r] = w * sp * (eb - R(2) * t * da);
+                obuf[1][j * (M + 1) + r] = w * sp;
+                obuf[2][j * (M + 1) + r] = eb * t + sp * da;
                 c2 = R(-2) * w * t * sp * da;
             }
             cbuf[r * M + j] = c2;
         }
         __syncthreads();
+        store_unit_tile<R, M>(obuf[0], alpha_out, lo, nat, H, mu0, lane);
+        store_unit_tile<R, M>(obuf[1], beta_out, lo, nat, H, mu0, lane);
+        store_unit_tile<R, M>(obuf[2], gamma_out, lo, nat, H, mu0, lane);
 #pragma unroll
         for (int dt = 0; dt < DT; ++dt) {
             const int nu = dt * M + j;
