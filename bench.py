@@ -45,58 +45,120 @@ def parse():
     p.add_argument("--no-comparator", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-structures", type=int, default=256)
+    p.add_argument("--cpu-seconds", type=float, default=10.0,
+                   help="repeat the oracle over the sample until this much time has passed")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also run one device-to-device copy of this many MiB (a known-size kernel that "
                         "calibrates hardware byte counters)")
     return p.parse_args()
 
 
-# ------------------------------------------------------------ FLOP model
+# ------------------------------------------------------------ work model
 #
-# Algorithmic FLOPs per unit of work of each kernel, counted from the formulas
-# the kernel evaluates (FMA = 2, other arithmetic and transcendental = 1).
-# K = basis size + 1, N = channels, LM = 24 harmonics (l <= 4), D descriptors.
+# Algorithmic work of each kernel per launch, counted from the formulas it
+# evaluates: FLOPs with FMA = 2 and every other arithmetic operation or
+# transcendental = 1; bytes = every array the kernel must read or write, each
+# counted once (neighbour records 4 reals per pair; per-atom and per-structure
+# arrays at their size; gathers of neighbour data and block-partial reduction
+# rows are not algorithmic and are not counted).
+# K = basis size + 1, N = radial/angular channels, LM = 24 harmonics (l <= 4),
+# D = descriptor length, H = hidden units, T = species.
 
 Y_VAL = 82      # the 24 real solid harmonics of a unit vector
 Y_DIR = 214     # harmonics and their derivative along one vector (dual numbers)
 Y_GRAD = 478    # harmonics and their full gradient (dual numbers)
+PAIR_GEOM = 9   # |r| (3 FMA + sqrt), 1/r, unit vector
 
 
 def basis_flops(K, deriv):
-    # x, y, sincospi, cutoff (~13) + per k: value 3 (+ derivative 6) + recurrence 2 (+ 4)
-    return 13 + K * (3 + (6 if deriv else 0)) + (K - 1) * (2 + (4 if deriv else 0))
+    # setup (y, x, sincospi, cutoff and its slope) 13; per k: f_k and the
+    # recurrence 4 (+ f_k' and the derivative recurrence 8)
+    return 13 + K * (12 if deriv else 4)
 
 
-def kernel_flops(name, md, npairs, nang, natoms):
+def work_model(name, md, n):
+    """(flops, bytes) of one launch of kernel `name`; n holds the batch counts."""
     KR, KA = md["basis_r"] + 1, md["basis_a"] + 1
     NR, NA = md["n_max_r"] + 1, md["n_max_a"] + 1
     T, H, L = md["num_types"], md["hidden"], md["l_max"]
     LM = (L + 1) ** 2 - 1
-    D = NR + NA * (L + (md["l_max_4b"] == 2) + (md["l_max_5b"] == 1))
+    h4, h5 = md["l_max_4b"] == 2, md["l_max_5b"] == 1
+    D = NR + NA * (L + h4 + h5)
+    npr, nang, na, ns, r = n["pairs"], n["angular_pairs"], n["atoms"], n["structures"], n["real_bytes"]
+    rec = 4 * r * npr                    # neighbour records
+    rec_ang = 4 * r * nang               # angular records only
+    idx = na * (8 + 4 + 4 + 8 * T)       # row offset, type, structure, per-species counts
+    B_atom = 2 * NA * LM + (50 * NA if h4 else 0) + (15 * NA if h5 else 0)  # dE/dA from e and A
     if name == "descriptor":
-        rad = 6 + basis_flops(KR, False) + KR
-        ang = 4 + basis_flops(KA, False) + Y_VAL + 2 * NA * KA + 2 * NA * LM
-        atom = T * 2 * NR * KR + 2 * NA * LM
-        return npairs * rad + nang * ang + natoms * atom
-    if name == "force":
-        rad = 6 + 1 + 3 + basis_flops(KR, True) + 3 * KR + 3
-        ang = basis_flops(KA, True) + Y_GRAD + 8 * NA * KA + 8 * NA * LM + 2 * LM * 5 + 12
-        return npairs * (rad + 18) + nang * ang
-    if name == "tangent":
-        rad = 6 + 1 + 3 + 15 + 5 + basis_flops(KR, True) + 2 * KR
-        ang = basis_flops(KA, True) + Y_DIR + 4 * LM + 4 * NA * KA + 4 * NA * LM + NA
-        atom = T * 2 * NR * KR + 4 * NA * LM
-        return npairs * rad + nang * ang + natoms * atom
-    if name == "angular_coeff_grad":
-        per = 6 + 1 + 3 + 15 + 5 + basis_flops(KA, True) + Y_DIR + 4 * LM + 6 * NA * LM + NA + 4 * NA * KA
-        return nang * per
+        pair_r = PAIR_GEOM + basis_flops(KR, False) + KR
+        pair_a = basis_flops(KA, False) + Y_VAL + 2 * NA * KA + 2 * NA * LM
+        atom = T * 2 * NR * KR + 2 * NA * LM + (40 * NA if h4 else 0)
+        return (npr * pair_r + nang * pair_a + na * atom,
+                rec + idx + na * r * (D + NA * LM + T * KR))
     if name == "network_forward":
-        return natoms * (D + H * (4 * D + 6) + 2 * NA * LM + T * 2 * NR * KR)
+        return (na * (2 * D + H * (2 * D + 2) + H * (2 * D + 4) + 2 * H),
+                na * (4 + r * (D + 1 + D + H)))
+    if name == "force":
+        pair_r = PAIR_GEOM + basis_flops(KR, True) + 2 * KR + 3 + 6 + 18
+        pair_a = basis_flops(KA, True) + Y_GRAD + 4 * NA * KA + 4 * NA * LM + 11 * LM + 12
+        atom = B_atom + T * 2 * NR * KR
+        return (npr * pair_r + nang * pair_a + na * atom,
+                rec + 4 * npr + idx + na * r * (NA * LM + D + 3 + 9) + rec)
+    if name == "force_gather":
+        return (npr * 3, rec + 4 * npr + na * (8 + 2 * 3 * r))
+    if name == "tangent":
+        pair_r = PAIR_GEOM + 24 + basis_flops(KR, True) + 5 + 2 * KR
+        pair_a = basis_flops(KA, True) + Y_DIR + 4 * LM + 4 * NA * KA + NA + 4 * NA * LM
+        atom = T * 2 * NR * KR + 4 * NA * LM + (60 * NA if h4 else 0)
+        return (npr * pair_r + nang * pair_a + na * atom,
+                rec + idx + na * r * (3 + NA * LM + D + NA * LM + T * KR) + ns * 72)
     if name == "network_backward":
-        return natoms * (D + H * (4 * D + 14) + 3 * D + 4 * NA * LM)
+        return (na * (H * (2 * D) + H * 14 + H * (2 * D) + 3 * D),
+                na * (4 + r * (3 * D + H + 3 * H)) + ns * 8)
+    if name == "angular_coeff_grad":
+        pair = (PAIR_GEOM + 24 + 5 + basis_flops(KA, True) + Y_DIR + 4 * LM
+                + 6 * NA * LM + NA + 4 * NA * KA)
+        atom = 3 * B_atom
+        return (nang * pair + na * atom,
+                rec_ang + idx + na * r * (3 + 2 * NA * LM + 2 * D) + ns * 72)
     if name == "outer_grad":
-        return natoms * (T * NR * KR * 4 + H * D * 4 + 2 * H)
+        return (na * (4 * H * D + 2 * H + 4 * T * NR * KR),
+                na * (4 + r * (4 * D + 3 * H + 2 * T * KR)))
     return None
+
+
+def source_digest():
+    """SHA-256 over the HIP sources of the library (any edit changes it)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_19557_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".inc", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    for line in open(path):
+        if line.startswith("source-sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 6 and cells[0] == kernel:
+            try:
+                val = float(cells[5])
+            except ValueError:
+                pass
+    if digest != source_digest() or val is None:
+        return None
+    return val
 
 
 # ------------------------------------------------------------------- main
@@ -193,14 +255,29 @@ def main():
         log(f"  kernel {name:22s} launches {n:4d}  avg {tot / n * 1e3:9.2f} us")
     dom = max(rows, key=lambda r: r[2] * (r[1] / args.profile_steps))
     name, n, avg_ms = dom
-    fl = kernel_flops(name, w.model, nb.num_pairs, nb.num_angular_pairs, host.num_atoms)
-    peak = PEAK_FP64_TFLOPS if w.dtype == "f64" else PEAK_FP32_TFLOPS
+    counts = {"pairs": nb.num_pairs, "angular_pairs": nb.num_angular_pairs, "atoms": host.num_atoms,
+              "structures": host.num_structures, "real_bytes": 8 if w.dtype == "f64" else 4}
+    work = work_model(name, w.model, counts)
+    peak_alu = PEAK_FP64_TFLOPS if w.dtype == "f64" else PEAK_FP32_TFLOPS
     roof = None
-    if fl is not None:
-        achieved = fl / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "flops_per_launch": int(fl), "avg_launch_us": round(avg_ms * 1e3, 2)}
+    if work is not None:
+        fl, by = work
+        sec = avg_ms * 1e-3
+        t_alu, t_hbm = fl / (peak_alu * 1e12), by / (PEAK_HBM_GBS * 1e9)
+        traffic = measured_traffic(name, args.workload)
+        if t_alu >= t_hbm:
+            achieved, peak = fl / sec / 1e12, peak_alu
+            roof = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                    "unit": "TFLOP/s"}
+        else:
+            achieved, peak = by / sec / 1e9, PEAK_HBM_GBS
+            roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": peak,
+                    "unit": "GB/s"}
+        roof.update({"frac": round(achieved / peak, 4), "traffic": None if traffic is None else int(traffic),
+                     "flops_per_launch": int(fl), "bytes_per_launch": int(by),
+                     "alu_frac": round(fl / sec / 1e12 / peak_alu, 4),
+                     "hbm_frac": round(by / sec / 1e9 / PEAK_HBM_GBS, 4),
+                     "avg_launch_us": round(avg_ms * 1e3, 2)})
     kernel_table = {r[0]: round(r[2] * 1e3, 2) for r in rows}
 
     # comparator: plain PyTorch autograd double backward on the same GPU
@@ -248,12 +325,18 @@ def main():
         Et_h = targets.energy[:n_s].cpu().numpy()
         Ft_h = targets.force[:a0].double().cpu().numpy()
         Wt_h = targets.virial[:n_s].cpu().numpy()
-        t0 = time.perf_counter()
-        O.loss_and_grad(om, th_h, qs_h, sub, Et_h, Ft_h, Wt_h, w.lambdas, nthreads=cores)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(n_s / dt, 2), "unit": "structures/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {n_s} structures of the workload, FP64 loss + gradient, {dt:.2f} s"}
-        log(f"cpu oracle {n_s / dt:.1f} structures/s on {cores} threads")
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.loss_and_grad(om, th_h, qs_h, sub, Et_h, Ft_h, Wt_h, w.lambdas, nthreads=cores)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds:
+                break
+        rate = reps * n_s / dt
+        cpu = {"value": round(rate, 2), "unit": "structures/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {n_s} structures of the workload x {reps} repetitions, FP64 loss + gradient, "
+                         f"{dt:.1f} s"}
+        log(f"cpu oracle {rate:.1f} structures/s on {cores} threads ({reps} x {n_s} structures, {dt:.1f} s)")
 
     out = {
         "metric": "structures/s for NEP E/F/virial loss+param-grad; % HBM/VALU roofline",
@@ -268,8 +351,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if w.dtype == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {host.num_structures} fcc cells, {host.num_atoms} atoms, "
-                               f"{nb.num_pairs} pairs (rc 6/4 A, n_max 6/4, basis 8/8, l_max 4, 30 neurons)",
+        "config": {"workload": f"{args.workload}: {w.description}",
                    "structures": host.num_structures, "atoms": host.num_atoms, "pairs": nb.num_pairs,
                    "angular_pairs": nb.num_angular_pairs, "parallelism": "single GPU"},
         "roofline": roof,

@@ -63,6 +63,19 @@ enum {
 
 enum { NEP_F32 = 0, NEP_F64 = 1 };
 
+/* Launch plan: the tile shapes of the pair sweeps and of the gradient
+ * reductions. Any zero field takes its default. Results differ between plans
+ * only by floating-point summation order. nep_autotune picks one by timing
+ * the candidates on the caller's batch. */
+typedef struct {
+    int32_t team_descriptor;   /* lanes per atom in the descriptor sweep: 4, 8 or 16 (default 8) */
+    int32_t team_force;        /* lanes per atom in the force sweep and force gather (default 8) */
+    int32_t team_tangent;      /* lanes per atom in the tangent sweep (default 8) */
+    int32_t team_coeff_grad;   /* lanes per atom in the angular coefficient-gradient sweep (default 8) */
+    int32_t coeff_grad_blocks; /* grid cap of that sweep = its FP64 partial rows, 1..65536 (default 2048) */
+    int32_t outer_chunk;       /* atoms per work item of the network/radial outer products, 8..4096 (default 64) */
+} nep_plan;
+
 /* Model hyper-parameters (the model keys of the paper's input file, Table I). */
 typedef struct {
     int32_t num_types;  /* T >= 1 species */
@@ -77,6 +90,8 @@ typedef struct {
     int32_t dtype;      /* NEP_F32 or NEP_F64 */
     double rc_r;        /* radial cutoff (Angstrom) */
     double rc_a;        /* angular cutoff, 0 < rc_a <= rc_r */
+    const nep_plan* plan; /* host, launch plan or NULL for the defaults; read during each call only.
+                             The workspace size depends on it. */
 } nep_model;
 
 /* A packed batch of fully periodic structures. Structure s owns atoms
@@ -136,8 +151,13 @@ nep_status nep_workspace_size(const nep_model* model, int32_t num_structures, in
 
 /* Builds the neighbour lists of a batch (once per dataset; the paper keeps
  * them on the GPU, Results, "Training efficiency"). Cutoffs from the model.
+ * Cell lists: each cell is binned into slabs at least r_c^R wide along every
+ * lattice direction (at most one bin per atom); every atom scans the bins
+ * within reach, periodic images included, with distances tested in FP64.
+ * Positions need not be wrapped into the cell. Rows are deterministic.
  * On NEP_ERR_CAPACITY nbr->num_pairs holds the required pair count; grow
- * nbr->pairs and call again. ws must hold nep_workspace_size(..., 0) bytes. */
+ * nbr->pairs and call again. ws must hold nep_workspace_size(..., 0) bytes
+ * (the bins live there during the call). */
 nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, nep_neighbors* nbr, void* ws,
                                size_t ws_bytes, void* stream);
 
@@ -169,6 +189,21 @@ nep_status nep_loss_and_grad(const nep_model* model, const void* theta, const vo
 nep_status nep_backward(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
                         const nep_neighbors* nbr, const double* dE, const void* dF, const double* dW, void* grad,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* Autotuner of the launch plan (the tiling choice of the packed batch). Times
+ * nep_loss_and_grad on this batch under candidate plans, `repeats` timed runs
+ * each after one warm-up, with HIP events around every kernel launch:
+ *   phase 1: team sizes 4, 8, 16 in all four pair sweeps; each sweep kernel
+ *            keeps its fastest;
+ *   phase 2: (coeff_grad_blocks, outer_chunk) pairs, chosen by the summed time
+ *            of the two kernels and the reductions that read their rows.
+ * Candidates whose workspace exceeds ws_bytes or whose LDS exceeds a CU are
+ * skipped. Writes the chosen plan to *plan_out (host); model->plan is ignored.
+ * The arguments are those of nep_loss_and_grad (loss and grad are overwritten).
+ * Synchronises the stream; clears event records of nep_profile_enable. */
+nep_status nep_autotune(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                        const nep_neighbors* nbr, const nep_targets* targets, double* loss, void* grad, void* ws,
+                        size_t ws_bytes, int32_t repeats, nep_plan* plan_out, void* stream);
 
 /* One Adam/AMSGrad step t (1-based) of Eqs. (8)-(13), in place on theta, m, v,
  * vmax (all [P] of dtype; vmax unused when cfg->amsgrad = 0, may be NULL). */

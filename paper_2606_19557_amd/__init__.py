@@ -8,8 +8,10 @@ from .nep import (  # noqa: F401
     NEPFunction,
     Neighbors,
     NepError,
+    Plan,
     Targets,
     nep_adam_step,
+    nep_autotune,
     nep_backward,
     nep_build_neighbors,
     nep_descriptor_scale,

@@ -105,7 +105,33 @@ const ShapeEntry* find_shape(const Dims& d) {
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs) {
+nep_status resolve_plan(const nep_plan* p, Plan* out) {
+    Plan q{kTeam, kTeam, kTeam, kTeam, kMaxAngRows, kOuterChunk};
+    if (p) {
+        const int32_t teams[4] = {p->team_descriptor, p->team_force, p->team_tangent, p->team_coeff_grad};
+        int* dst[4] = {&q.team_desc, &q.team_force, &q.team_tangent, &q.team_cg};
+        for (int k = 0; k < 4; ++k) {
+            if (teams[k] == 0) continue;
+            if (teams[k] != 4 && teams[k] != 8 && teams[k] != 16)
+                return fail(NEP_ERR_INVALID_ARG, "plan team size %d is not 4, 8 or 16", teams[k]);
+            *dst[k] = teams[k];
+        }
+        if (p->coeff_grad_blocks != 0) {
+            if (p->coeff_grad_blocks < 1 || p->coeff_grad_blocks > 65536)
+                return fail(NEP_ERR_INVALID_ARG, "plan coeff_grad_blocks %d outside [1, 65536]", p->coeff_grad_blocks);
+            q.cg_blocks = p->coeff_grad_blocks;
+        }
+        if (p->outer_chunk != 0) {
+            if (p->outer_chunk < 8 || p->outer_chunk > 4096)
+                return fail(NEP_ERR_INVALID_ARG, "plan outer_chunk %d outside [8, 4096]", p->outer_chunk);
+            q.outer_chunk = p->outer_chunk;
+        }
+    }
+    *out = q;
+    return NEP_OK;
+}
+
+Layout make_layout(const Dims& dm, const Plan& plan, bool f64, int Ns, long Na, long pairs) {
     Layout L{};
     const size_t r = f64 ? 8 : 4;
     const size_t na = size_t(Na > 0 ? Na : 0), ns = size_t(Ns > 0 ? Ns : 0);
@@ -139,13 +165,14 @@ Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs) {
     L.ebar = take(8 * ns);
     L.Ubar = take(8 * ns * 9);
     L.lossp = take(8 * ns * 3);
-    const long tiles = (Na + kBlock / kTeam - 1) / (kBlock / kTeam);
-    L.ang_rows = int(tiles < kMaxAngRows ? tiles : kMaxAngRows);
+    const long teams = kBlock / plan.team_cg;
+    const long tiles = (Na + teams - 1) / teams;
+    L.ang_rows = int(tiles < plan.cg_blocks ? tiles : plan.cg_blocks);
     if (L.ang_rows < 1) L.ang_rows = 1;
-    // outer reduction: one species-tagged row per chunk of kOuterChunk atoms of
+    // outer reduction: one species-tagged row per chunk of outer_chunk atoms of
     // one species; at most ceil(Na / chunk) + T chunks.
-    L.outer_chunk = kOuterChunk;
-    L.outer_rows = int((Na + kOuterChunk - 1) / kOuterChunk) + dm.T;
+    L.outer_chunk = plan.outer_chunk;
+    L.outer_rows = int((Na + plan.outer_chunk - 1) / plan.outer_chunk) + dm.T;
     const size_t W1 = size_t(dm.D + 2) * dm.H + size_t(dm.T) * dm.NR * dm.KR;
     L.outer_part = take(8 * (W1 + 1) * size_t(L.outer_rows));
     L.ang_part = take(8 * size_t(dm.offN - dm.offA) * size_t(L.ang_rows));
@@ -230,15 +257,7 @@ static nep_status base_ctx(const nep_model* model, const void* theta, const void
                     model->n_max_r, model->n_max_a, model->basis_r, model->basis_a, model->l_max, model->l_max_4b,
                     model->l_max_5b);
     c->f64 = model->dtype == NEP_F64;
-    {
-        // LDS of the angular-coefficient gradient block: accumulator, team
-        // slots, the atoms' adjoints and the exchange buffers (<= 160 KB)
-        const size_t r = c->f64 ? 8 : 4, teams = kBlock / kTeam, nk = size_t(c->dm.NA) * c->dm.KA;
-        const size_t shm = r * (size_t(c->dm.T) * c->dm.T * nk + teams * nk + teams * 2 * c->dm.NA * c->dm.LM +
-                                teams * kTeam * (c->dm.NA + c->dm.KA + 1)) + sizeof(int) * teams;
-        if (shm > 160 * 1024)
-            return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block too large for LDS (%zu bytes)", shm);
-    }
+    if ((s = resolve_plan(model->plan, &c->plan))) return s;
     c->stream = static_cast<hipStream_t>(stream);
     c->mode = mode;
     c->Ns = batch->num_structures;
@@ -290,7 +309,9 @@ nep_status nep_workspace_size(const nep_model* model, int32_t num_structures, in
     if (s) return s;
     if (!bytes || num_structures < 0 || num_atoms < 0 || num_pairs < 0)
         return fail(NEP_ERR_INVALID_ARG, "bad workspace query");
-    *bytes = make_layout(d, model->dtype == NEP_F64, num_structures, long(num_atoms), long(num_pairs)).total;
+    Plan plan;
+    if ((s = resolve_plan(model->plan, &plan))) return s;
+    *bytes = make_layout(d, plan, model->dtype == NEP_F64, num_structures, long(num_atoms), long(num_pairs)).total;
     return NEP_OK;
 }
 
@@ -416,6 +437,115 @@ nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int3
     else
         NEP_LAUNCH("scale", (k_scale<float>), dim3(int(num_descriptors)), dim3(kRedBlock), 0, st, long(num_atoms),
                    int(num_descriptors), static_cast<const float*>(descriptor), static_cast<float*>(q_scale));
+    return NEP_OK;
+}
+
+nep_status nep_autotune(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
+                        const nep_neighbors* nbr, const nep_targets* targets, double* loss, void* grad, void* ws,
+                        size_t ws_bytes, int32_t repeats, nep_plan* plan_out, void* stream) {
+    clear_error();
+    if (!model || !plan_out) return fail(NEP_ERR_INVALID_ARG, "model or plan_out is NULL");
+    if (repeats < 1 || repeats > 1000) return fail(NEP_ERR_INVALID_ARG, "repeats %d outside [1, 1000]", repeats);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool was_on = g_prof_on;
+    nep_model m = *model;
+    // average milliseconds per launch of each kernel under plan p; +inf if the
+    // plan does not fit (workspace or LDS)
+    auto measure = [&](const nep_plan& p, std::map<std::string, double>* avg) -> nep_status {
+        avg->clear();
+        m.plan = &p;
+        size_t need = 0;
+        nep_status s = nep_workspace_size(&m, batch ? batch->num_structures : 0, batch ? batch->num_atoms : 0,
+                                          nbr ? nbr->num_pairs : 0, &need);
+        if (s) return s;
+        if (need > ws_bytes) return NEP_ERR_WORKSPACE;
+        profile_clear();
+        g_prof_on = false;
+        s = nep_loss_and_grad(&m, theta, q_scale, batch, nbr, targets, loss, grad, nullptr, nullptr, nullptr, ws,
+                              ws_bytes, stream);
+        if (s) return s;
+        g_prof_on = true;
+        for (int r = 0; r < repeats && !s; ++r)
+            s = nep_loss_and_grad(&m, theta, q_scale, batch, nbr, targets, loss, grad, nullptr, nullptr, nullptr, ws,
+                                  ws_bytes, stream);
+        g_prof_on = false;
+        if (s) return s;
+        if (hipStreamSynchronize(st) != hipSuccess) return fail(NEP_ERR_HIP, "stream synchronise failed");
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        for (ProfRec* rec : g_prof) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, rec->a, rec->b) != hipSuccess) return fail(NEP_ERR_HIP, "event timing failed");
+            (*avg)[rec->name] += ms / repeats;
+        }
+        return NEP_OK;
+    };
+    auto fits = [](nep_status s) { return s == NEP_OK; };
+    auto skippable = [](nep_status s) { return s == NEP_ERR_WORKSPACE || s == NEP_ERR_UNSUPPORTED; };
+    auto get = [](const std::map<std::string, double>& a, const char* k) {
+        auto it = a.find(k);
+        return it == a.end() ? 0.0 : it->second;
+    };
+    nep_plan best{8, 8, 8, 8, kMaxAngRows, kOuterChunk};
+    // phase 1: team sizes, all four sweeps at once; each kernel keeps its fastest
+    {
+        const int cand[3] = {4, 8, 16};
+        double tb[4] = {1e300, 1e300, 1e300, 1e300};
+        const char* names[4][2] = {{"descriptor", nullptr}, {"force", "force_gather"}, {"tangent", nullptr},
+                                   {"angular_coeff_grad", nullptr}};
+        int32_t* field[4] = {&best.team_descriptor, &best.team_force, &best.team_tangent, &best.team_coeff_grad};
+        for (int k = 0; k < 3; ++k) {
+            nep_plan p{cand[k], cand[k], cand[k], cand[k], kMaxAngRows, kOuterChunk};
+            std::map<std::string, double> avg;
+            nep_status s = measure(p, &avg);
+            if (skippable(s)) {
+                // the LDS of the coefficient sweep may not fit: time the others
+                p.team_coeff_grad = 8;
+                s = measure(p, &avg);
+                if (fits(s)) avg.erase("angular_coeff_grad");
+            }
+            if (skippable(s)) continue;
+            if (s) {
+                g_prof_on = was_on;
+                return s;
+            }
+            for (int q = 0; q < 4; ++q) {
+                if (!avg.count(names[q][0])) continue;
+                const double t = get(avg, names[q][0]) + (names[q][1] ? get(avg, names[q][1]) : 0.0);
+                if (t < tb[q]) {
+                    tb[q] = t;
+                    *field[q] = cand[k];
+                }
+            }
+        }
+    }
+    // phase 2: grid of the coefficient sweep and chunk of the outer products
+    {
+        const int cand[4][2] = {{2048, 64}, {1024, 128}, {4096, 32}, {512, 256}};
+        double tb = 1e300;
+        nep_plan keep = best;
+        for (int k = 0; k < 4; ++k) {
+            nep_plan p = best;
+            p.coeff_grad_blocks = cand[k][0];
+            p.outer_chunk = cand[k][1];
+            std::map<std::string, double> avg;
+            nep_status s = measure(p, &avg);
+            if (skippable(s)) continue;
+            if (s) {
+                g_prof_on = was_on;
+                return s;
+            }
+            const double t = get(avg, "angular_coeff_grad") + get(avg, "outer_grad") + get(avg, "reduce_stage") +
+                             get(avg, "final_reduce");
+            if (t < tb) {
+                tb = t;
+                keep = p;
+            }
+        }
+        best = keep;
+    }
+    profile_clear();
+    g_prof_on = was_on;
+    *plan_out = best;
     return NEP_OK;
 }
 

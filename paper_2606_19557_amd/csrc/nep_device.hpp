@@ -96,6 +96,18 @@ __device__ __forceinline__ void cheb_basis(R r, R rc, R inv_rc, R* f, R* fp) {
     }
 }
 
+// 16-byte vector of R (LDS and global vector loads)
+template <typename R>
+struct VecOf;
+template <>
+struct VecOf<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct VecOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
 // ---------------------------------------------------------------- number types
 
 // Value and one directional derivative.
@@ -279,7 +291,10 @@ __device__ __forceinline__ R team_sum(R v) {
 template <typename R, int NA, int LM, int S>
 struct MomentExchange {
     static constexpr int OWN = (LM + S - 1) / S;
-    static constexpr int SLOT = NA + LM + 1;  // +1 spreads the lane slots over banks
+    // Lane slot of NA + LM values padded to 1 (mod 4) elements: the slots of
+    // one team and the team blocks of one wave then fall on distinct LDS banks
+    // for the stores and for both the broadcast and the per-lane loads.
+    static constexpr int SLOT = NA + LM + ((1 - (NA + LM)) % 4 + 4) % 4;
     static constexpr int TEAM_FLOATS = S * SLOT;
 
     __device__ static void wave_fence() {

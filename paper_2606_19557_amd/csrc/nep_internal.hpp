@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/nep.h"
 #include "nep_device.hpp"
@@ -44,9 +45,24 @@ void profile_end(void* token, hipStream_t st);
 
 enum class Mode { Descriptors, Forward, LossGrad, Backward };
 
+// A resolved launch plan (nep_plan with the defaults filled in).
+struct Plan {
+    int team_desc, team_force, team_tangent, team_cg;
+    int cg_blocks, outer_chunk;
+};
+
+// Team size (lanes per atom) of the pair sweeps and the grid defaults.
+constexpr int kTeam = 8;
+constexpr int kMaxAngRows = 2048;
+constexpr int kOuterChunk = 64;
+
+// Defaults for zero fields; NEP_ERR_INVALID_ARG for values out of range.
+nep_status resolve_plan(const nep_plan* p, Plan* out);
+
 // Everything one call needs, already validated.
 struct Ctx {
     Dims dm;
+    Plan plan;
     bool f64;
     hipStream_t stream;
     Mode mode;
@@ -95,12 +111,21 @@ struct Layout {
     int outer_rows, ang_rows, outer_chunk;
 };
 
-Layout make_layout(const Dims& dm, bool f64, int Ns, long Na, long pairs);
+Layout make_layout(const Dims& dm, const Plan& plan, bool f64, int Ns, long Na, long pairs);
 
-// Team size (lanes per atom) of the pair sweeps and the grid caps.
-constexpr int kTeam = 8;
-constexpr int kMaxAngRows = 512;
-constexpr int kOuterChunk = 64;
+// Calls f(std::integral_constant<int, S>) for the team size s in {4, 8, 16}.
+template <typename T, class F>
+T with_team_size(int s, F&& f) {
+    switch (s) {
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        default: return f(std::integral_constant<int, 8>{});
+    }
+}
+template <class F>
+nep_status with_team(int s, F&& f) {
+    return with_team_size<nep_status>(s, static_cast<F&&>(f));
+}
 
 // Per-shape pipeline (forward / loss+grad / backward / descriptors).
 using ShapeFn = nep_status (*)(const Ctx&);

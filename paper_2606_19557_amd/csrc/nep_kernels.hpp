@@ -61,40 +61,39 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
         R Sb[KR];
 #pragma unroll
         for (int k = 0; k < KR; ++k) Sb[k] = R(0);
-        // angular pairs, one batch of S per iteration (team-uniform trip count)
-        for (int base = 0; base < ang; base += S) {
+        // batches of S pairs (team-uniform trip count); the record of the next
+        // batch is loaded one batch ahead. Batches that start inside the
+        // angular prefix go through the moment exchange.
+        Rec<R> nx{};
+        if (lane < tot) nx = pairs[p + lane];
+        for (int base = 0; base < tot; base += S) {
             const int k = base + lane;
+            const Rec<R> pr = nx;
+            if (k + S < tot) nx = pairs[p + k + S];
+            const bool angb = base < ang;
             R g[NA], Y[LM];
 #pragma unroll
             for (int n = 0; n < NA; ++n) g[n] = R(0);
 #pragma unroll
             for (int lm = 0; lm < LM; ++lm) Y[lm] = R(0);
-            if (k < ang) {
-                const Rec<R> pr = pairs[p + k];
+            if (k < tot) {
                 const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
                 R f[KR];
                 cheb_basis<R, KR, false>(r, rcR, irR, f, nullptr);
 #pragma unroll
                 for (int kk = 0; kk < KR; ++kk) Sb[kk] += f[kk];
-                R fa[KA];
-                cheb_basis<R, KA, false>(r, rcA, irA, fa, nullptr);
-                const R ir = R(1) / r;
-                solid_harmonics<R, R, L>(pr.x * ir, pr.y * ir, pr.z * ir, Y);
+                if (k < ang) {
+                    R fa[KA];
+                    cheb_basis<R, KA, false>(r, rcA, irA, fa, nullptr);
+                    const R ir = R(1) / r;
+                    solid_harmonics<R, R, L>(pr.x * ir, pr.y * ir, pr.z * ir, Y);
 #pragma unroll
-                for (int n = 0; n < NA; ++n)
+                    for (int n = 0; n < NA; ++n)
 #pragma unroll
-                    for (int kk = 0; kk < KA; ++kk) g[n] += cA[n * KA + kk] * fa[kk];
+                        for (int kk = 0; kk < KA; ++kk) g[n] += cA[n * KA + kk] * fa[kk];
+                }
             }
-            X::accumulate(tbuf, lane, g, Y, acc);
-        }
-        // radial-only pairs
-        for (int k = ang + lane; k < tot; k += S) {
-            const Rec<R> pr = pairs[p + k];
-            const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
-            R f[KR];
-            cheb_basis<R, KR, false>(r, rcR, irR, f, nullptr);
-#pragma unroll
-            for (int kk = 0; kk < KR; ++kk) Sb[kk] += f[kk];
+            if (angb) X::accumulate(tbuf, lane, g, Y, acc);
         }
         p += tot;
 #pragma unroll
@@ -270,8 +269,20 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
             }
         }
         const R* __restrict__ cA = theta + dm.offA + (long)((a * T + b) * NA) * KA;
+        // the next record and reverse index are loaded one iteration ahead
+        Rec<R> nx{};
+        int nrev = -1;
+        if (lane < tot) {
+            nx = pairs[p + lane];
+            nrev = reverse[p + lane];
+        }
         for (int k = lane; k < tot; k += S) {
-            const Rec<R> pr = pairs[p + k];
+            const Rec<R> pr = nx;
+            const int q = nrev;
+            if (k + S < tot) {
+                nx = pairs[p + k + S];
+                nrev = reverse[p + k + S];
+            }
             const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
             const R ir = R(1) / r;
             const R u[3] = {pr.x * ir, pr.y * ir, pr.z * ir};
@@ -317,7 +328,6 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
 #pragma unroll
                 for (int d = 0; d < 3; ++d) hv[d] += sY * u[d] + (G[d] - lY * u[d]) * ir;
             }
-            const int q = reverse[p + k];
             if (q >= 0) {
                 Rec<R> ho;
                 ho.x = -hv[0];
@@ -421,33 +431,43 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
         R Sb[KR];
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) Sb[kk] = R(0);
+        // the next batch's record is loaded one batch ahead; the neighbour's
+        // seed (a dependent load) is issued before the basis is evaluated
+        Rec<R> nx{};
+        if (lane < tot) nx = pairs[p + lane];
         for (int base = 0; base < tot; base += S) {
             const int k = base + lane;
             const bool angb = base < ang;  // team-uniform: this batch starts inside the angular prefix
+            const Rec<R> pr = nx;
+            R uj[3] = {R(0), R(0), R(0)};
+            if (k < tot) {
+                const long j = rec_j(pr);
+#pragma unroll
+                for (int be = 0; be < 3; ++be) uj[be] = ubar[j * 3 + be];
+            }
+            if (k + S < tot) nx = pairs[p + k + S];
             R gpv[NA], g[NA], Y[LM], vdY[LM];
 #pragma unroll
             for (int n = 0; n < NA; ++n) gpv[n] = g[n] = R(0);
 #pragma unroll
             for (int lm = 0; lm < LM; ++lm) Y[lm] = vdY[lm] = R(0);
             if (k < tot) {
-                const Rec<R> pr = pairs[p + k];
-                const int j = rec_j(pr);
                 const R rv[3] = {pr.x, pr.y, pr.z};
-                R v[3];
-#pragma unroll
-                for (int be = 0; be < 3; ++be)
-                    v[be] = ui[be] - ubar[(long)j * 3 + be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
                 const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
                 const R ir = R(1) / r;
                 const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
-                const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
                 R f[KR], fp[KR];
                 cheb_basis<R, KR, true>(r, rcR, irR, f, fp);
+                R fa[KA], fap[KA];
+                if (k < ang) cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
+                R v[3];
+#pragma unroll
+                for (int be = 0; be < 3; ++be)
+                    v[be] = ui[be] - uj[be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
+                const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
 #pragma unroll
                 for (int kk = 0; kk < KR; ++kk) Sb[kk] += vu * fp[kk];
                 if (k < ang) {
-                    R fa[KA], fap[KA];
-                    cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
                     const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
                     D1<R> Yd[LM];
                     solid_harmonics<D1<R>, R, L>(dx, dy, dz, Yd);
@@ -564,12 +584,21 @@ template <typename R, class Sh, int S>
 struct CoeffGradSmem {
     static constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, TEAMS = kBlock / S;
     using X = MomentExchange<R, NA, KA, S>;
-    static size_t bytes(int T) {
-        return sizeof(R) * (size_t(T) * T * NA * KA + size_t(TEAMS) * NA * KA + size_t(TEAMS) * 2 * NA * LM +
-                            size_t(TEAMS) * X::TEAM_FLOATS) +
-               sizeof(int) * TEAMS;
-    }
+    // 16-byte vectors of R for the broadcast loads of Bp and Q
+    static constexpr int VEC = 16 / int(sizeof(R));
+    // per-team [Bp | Q] block: 2 NA LM values padded to a whole number of
+    // vectors and to 8 (mod 32) 4-byte words, so the teams of a wave read
+    // distinct banks
+    static constexpr int WORDS = 2 * NA * LM * int(sizeof(R)) / 4;
+    static constexpr int BQ_STRIDE = (WORDS + ((8 - WORDS) % 32 + 32) % 32) * 4 / int(sizeof(R));
+    __host__ __device__ static constexpr size_t align16(size_t n) { return (n * sizeof(R) + 15) / 16 * 16 / sizeof(R); }
+    // offsets (in R) of the regions: G, team slots, Bp/Q blocks, exchange
+    __host__ __device__ static size_t off_slot(int T) { return align16(size_t(T) * T * NA * KA); }
+    __host__ __device__ static size_t off_bq(int T) { return align16(off_slot(T) + size_t(TEAMS) * NA * KA); }
+    __host__ __device__ static size_t off_x(int T) { return off_bq(T) + size_t(TEAMS) * BQ_STRIDE; }
+    __host__ __device__ static size_t bytes(int T) { return sizeof(R) * (off_x(T) + size_t(TEAMS) * X::TEAM_FLOATS) + sizeof(int) * TEAMS; }
 };
+static_assert(CoeffGradSmem<float, Shape<9, 9, 7, 5, 4, 0, 0>, 8>::BQ_STRIDE % 4 == 0, "vector alignment");
 
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
@@ -579,19 +608,22 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
                      const R* __restrict__ dA_in, const R* __restrict__ e_in, const R* __restrict__ abar,
                      double* __restrict__ partial) {
     constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L, D = Sh::D;
-    using X = MomentExchange<R, NA, KA, S>;
-    constexpr int OWN = X::OWN, NK = NA * KA, TEAMS = kBlock / S;
-    extern __shared__ unsigned char smem_raw[];
+    using SM = CoeffGradSmem<R, Sh, S>;
+    using X = typename SM::X;
+    using V = typename VecOf<R>::type;
+    constexpr int OWN = X::OWN, NK = NA * KA, TEAMS = kBlock / S, VEC = SM::VEC;
+    static_assert(LM % VEC == 0, "harmonic rows are whole vectors");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = dm.T;
     const int G_len = T * T * NK;
     R* G = reinterpret_cast<R*>(smem_raw);
-    R* slot = G + G_len;                      // [TEAMS][NK]
-    R* BQ = slot + TEAMS * NK;                // [TEAMS][2][NA][LM]
-    R* xb = BQ + TEAMS * 2 * NA * LM;         // [TEAMS][exchange]
+    R* slot = G + SM::off_slot(T);            // [TEAMS][NK]
+    R* BQ = G + SM::off_bq(T);                // [TEAMS][BQ_STRIDE]: Bp[NA][LM], Q[NA][LM]
+    R* xb = G + SM::off_x(T);                 // [TEAMS][exchange]
     int* team_type = reinterpret_cast<int*>(xb + TEAMS * X::TEAM_FLOATS);
     for (int x = threadIdx.x; x < G_len; x += kBlock) G[x] = R(0);
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    R* myBp = BQ + team * 2 * NA * LM;
+    R* myBp = BQ + team * SM::BQ_STRIDE;
     R* myQ = myBp + NA * LM;
     R* tbuf = xb + team * X::TEAM_FLOATS;
     const R rcA = R(dm.rcA), irA = R(1.0 / dm.rcA);
@@ -623,40 +655,56 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
             for (int n = 0; n < NA; ++n)
 #pragma unroll
                 for (int o = 0; o < OWN; ++o) acc[n][o] = R(0);
+            // record one batch ahead; the neighbour's seed before the basis
+            Rec<R> nx{};
+            if (lane < ang) nx = pairs[p + lane];
             for (int base = 0; base < ang; base += S) {
                 const int k = base + lane;
+                const Rec<R> pr = nx;
+                R uj[3] = {R(0), R(0), R(0)};
+                if (k < ang) {
+                    const long j = rec_j(pr);
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) uj[be] = ubar[j * 3 + be];
+                }
+                if (k + S < ang) nx = pairs[p + k + S];
                 R P[NA], Rn[NA], fa[KA], fap[KA];
 #pragma unroll
                 for (int n = 0; n < NA; ++n) P[n] = Rn[n] = R(0);
 #pragma unroll
                 for (int kk = 0; kk < KA; ++kk) fa[kk] = fap[kk] = R(0);
                 if (k < ang) {
-                    const Rec<R> pr = pairs[p + k];
-                    const int j = rec_j(pr);
                     const R rv[3] = {pr.x, pr.y, pr.z};
-                    R v[3];
-#pragma unroll
-                    for (int be = 0; be < 3; ++be)
-                        v[be] = ui[be] - ubar[(long)j * 3 + be] -
-                                (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
                     const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
                     const R ir = R(1) / r;
                     const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
-                    const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
                     cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
+                    R v[3];
+#pragma unroll
+                    for (int be = 0; be < 3; ++be)
+                        v[be] = ui[be] - uj[be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
+                    const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
                     const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
                     D1<R> Yd[LM];
                     solid_harmonics<D1<R>, R, L>(dx, dy, dz, Yd);
+                    R vdy[LM];
+#pragma unroll
+                    for (int lm = 0; lm < LM; ++lm)
+                        vdy[lm] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
 #pragma unroll
                     for (int n = 0; n < NA; ++n) {
                         R pn = R(0), rn = R(0);
+                        const V* bp = reinterpret_cast<const V*>(myBp + n * LM);
+                        const V* qq = reinterpret_cast<const V*>(myQ + n * LM);
 #pragma unroll
-                        for (int lm = 0; lm < LM; ++lm) {
-                            const R y = Yd[lm].v;
-                            const R vdy = (Yd[lm].d - R(lm_degree<LM>(lm)) * y * vu) * ir;
-                            const R q = myQ[n * LM + lm];
-                            pn += myBp[n * LM + lm] * y + q * vdy;
-                            rn += q * y;
+                        for (int c = 0; c < LM / VEC; ++c) {
+                            const V bv = bp[c], qv = qq[c];
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) {
+                                const int lm = c * VEC + e;
+                                pn += bv[e] * Yd[lm].v + qv[e] * vdy[lm];
+                                rn += qv[e] * Yd[lm].v;
+                            }
                         }
                         P[n] = pn;
                         Rn[n] = rn * vu;

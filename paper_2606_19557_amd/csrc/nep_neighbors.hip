@@ -1,11 +1,15 @@
-// Neighbour lists of a packed batch of periodic structures.
+// Neighbour lists of a packed batch of periodic structures, built with cell lists.
 //
-// One lane per atom scans every atom of its structure and every periodic image
-// n with |s_j - s_i + n|_d < rc / w_d in each lattice direction d (s are
-// fractional coordinates, w the perpendicular cell widths), which is necessary
-// for |r_ij| < rc; the distance test is done in double precision. Rows are
-// written grouped by neighbour species, pairs inside the angular cutoff first
-// in each group, in (j, image) scan order, so the result is deterministic.
+// Each structure's cell is cut into n_d >= 1 bins along every lattice
+// direction d, each at least r_c wide across (n_d = floor(w_d / r_c), w_d the
+// perpendicular width), at most one bin per atom. Atoms are binned by their
+// wrapped fractional coordinates; a bin's atoms are kept in index order. One
+// lane per atom then scans the bins c + delta, |delta_d| <= ceil(r_c n_d / w_d):
+// bin (c + delta) mod n lies in periodic image floor((c + delta) / n), so thin
+// cells (n_d = 1, w_d < r_c) get their extra images from the same loop, and
+// each (j, image) is visited once. Distances are tested in double precision.
+// Rows are written grouped by neighbour species, pairs inside the angular
+// cutoff first in each group, in scan order, so the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -61,20 +65,155 @@ __device__ __forceinline__ int find_struct(const int64_t* __restrict__ off, int 
     return lo;
 }
 
-template <typename R, bool FILL>
+// Per structure: bins per lattice direction and the structure's bin count.
 __global__ void __launch_bounds__(kNbBlock)
-k_neighbors(int Ns, long Na, int T, const int64_t* __restrict__ off, const R* __restrict__ pos,
-            const int* __restrict__ types, const double* __restrict__ cells, double rcR, double rcA,
-            int* __restrict__ seg, int64_t* __restrict__ count_or_row, int* __restrict__ atom_struct,
-            Rec<R>* __restrict__ pairs) {
+k_cell_setup(int Ns, const int64_t* __restrict__ off, const double* __restrict__ cells, double rc,
+             int* __restrict__ sbins, int64_t* __restrict__ bin_base) {
+    const int s = blockIdx.x * kNbBlock + threadIdx.x;
+    if (s >= Ns) return;
+    const CellInfo ci = cell_info(cells + 9L * s);
+    const long n_at = off[s + 1] - off[s];
+    long nb[3];
+    for (int d = 0; d < 3; ++d) {
+        const double q = floor(ci.w[d] / rc);
+        nb[d] = q < 1.0 ? 1 : (q > 1024.0 ? 1024 : long(q));
+    }
+    const long cap = n_at > 1 ? n_at : 1;
+    while (nb[0] * nb[1] * nb[2] > cap) {  // at most one bin per atom
+        int dm = 0;
+        for (int d = 1; d < 3; ++d)
+            if (nb[d] > nb[dm]) dm = d;
+        nb[dm] -= 1;
+    }
+    for (int d = 0; d < 3; ++d) sbins[3 * s + d] = int(nb[d]);
+    bin_base[s + 1] = nb[0] * nb[1] * nb[2];
+}
+
+// Single-block exclusive scan in place: a[0] = 0, a[1..n] counts -> running sums.
+constexpr int kScanBlock = 1024;
+
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_counts(long n, int64_t* __restrict__ a) {
+    __shared__ int64_t buf[kScanBlock];
+    __shared__ int64_t carry_s;
+    if (threadIdx.x == 0) {
+        carry_s = 0;
+        a[0] = 0;
+    }
+    __syncthreads();
+    for (long base = 0; base < n; base += kScanBlock) {
+        const long i = base + threadIdx.x;
+        buf[threadIdx.x] = (i < n) ? a[i + 1] : 0;
+        __syncthreads();
+        for (int o = 1; o < kScanBlock; o <<= 1) {
+            const int64_t t = (threadIdx.x >= (unsigned)o) ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        const int64_t incl = buf[threadIdx.x] + carry_s;
+        if (i < n) a[i + 1] = incl;
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) carry_s = incl;
+        __syncthreads();
+    }
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kNbBlock) k_zero(long n, I* __restrict__ a) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+// Per atom: structure, wrapped position r - floor(f) H (f = r H^-1 the
+// fractional coordinates, wrapped into [0, 1)) and global bin index; counts
+// atoms per bin (bin_count[b + 1]).
+template <typename R>
+__global__ void __launch_bounds__(kNbBlock)
+k_bin_atoms(int Ns, long Na, const int64_t* __restrict__ off, const R* __restrict__ pos,
+            const double* __restrict__ cells, const int* __restrict__ sbins, const int64_t* __restrict__ bin_base,
+            int* __restrict__ atom_struct, int* __restrict__ atom_bin, double* __restrict__ wpos,
+            unsigned long long* __restrict__ bin_count) {
     const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
     if (i >= Na) return;
     const int s = find_struct(off, Ns, i);
     const CellInfo ci = cell_info(cells + 9L * s);
-    const long j0 = off[s], j1 = off[s + 1];
-    const double ri[3] = {double(pos[3 * i]), double(pos[3 * i + 1]), double(pos[3 * i + 2])};
-    double fi[3];
-    for (int d = 0; d < 3; ++d) fi[d] = ri[0] * ci.Hi[d] + ri[1] * ci.Hi[3 + d] + ri[2] * ci.Hi[6 + d];
+    const double r[3] = {double(pos[3 * i]), double(pos[3 * i + 1]), double(pos[3 * i + 2])};
+    double sh[3];
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+        const double f = r[0] * ci.Hi[d] + r[1] * ci.Hi[3 + d] + r[2] * ci.Hi[6 + d];
+        double n = floor(f), fw = f - n;
+        if (fw >= 1.0) {
+            n += 1.0;
+            fw = 0.0;
+        }
+        sh[d] = n;
+        const int nb = sbins[3 * s + d];
+        const int cd = int(fw * nb);
+        c[d] = cd < nb ? cd : nb - 1;
+    }
+    for (int x = 0; x < 3; ++x) wpos[3 * i + x] = r[x] - (sh[0] * ci.H[x] + sh[1] * ci.H[3 + x] + sh[2] * ci.H[6 + x]);
+    const int gb = int(bin_base[s] + (long(c[0]) * sbins[3 * s + 1] + c[1]) * sbins[3 * s + 2] + c[2]);
+    atom_struct[i] = s;
+    atom_bin[i] = gb;
+    atomicAdd(bin_count + gb + 1, 1ull);
+}
+
+// Scatter atoms into their bins (arbitrary order within a bin, fixed below).
+__global__ void __launch_bounds__(kNbBlock)
+k_bin_fill(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
+           unsigned int* __restrict__ cursor, int* __restrict__ bin_atoms) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i >= Na) return;
+    const int gb = atom_bin[i];
+    const unsigned int k = atomicAdd(cursor + gb, 1u);
+    bin_atoms[bin_start[gb] + k] = int(i);
+}
+
+// Each bin's atoms in increasing index order (insertion sort; bins are small).
+__global__ void __launch_bounds__(kNbBlock)
+k_bin_sort(long max_bins, const int64_t* __restrict__ nbins_total, const int64_t* __restrict__ bin_start,
+           int* __restrict__ bin_atoms) {
+    const long b = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (b >= max_bins || b >= *nbins_total) return;
+    const int64_t lo = bin_start[b], hi = bin_start[b + 1];
+    for (int64_t x = lo + 1; x < hi; ++x) {
+        const int v = bin_atoms[x];
+        int64_t y = x - 1;
+        while (y >= lo && bin_atoms[y] > v) {
+            bin_atoms[y + 1] = bin_atoms[y];
+            --y;
+        }
+        bin_atoms[y + 1] = v;
+    }
+}
+
+__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+
+template <typename R, bool FILL>
+__global__ void __launch_bounds__(kNbBlock)
+k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restrict__ cells, double rcR,
+            double rcA, const int* __restrict__ atom_struct, const int* __restrict__ atom_bin,
+            const double* __restrict__ wpos, const int* __restrict__ sbins, const int64_t* __restrict__ bin_base,
+            const int64_t* __restrict__ bin_start, const int* __restrict__ bin_atoms, int* __restrict__ seg,
+            int64_t* __restrict__ count_or_row, Rec<R>* __restrict__ pairs) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i >= Na) return;
+    const int s = atom_struct[i];
+    const CellInfo ci = cell_info(cells + 9L * s);
+    const int nb[3] = {sbins[3 * s], sbins[3 * s + 1], sbins[3 * s + 2]};
+    int c[3];
+    {
+        int loc = int(atom_bin[i] - bin_base[s]);
+        c[2] = loc % nb[2];
+        loc /= nb[2];
+        c[1] = loc % nb[1];
+        c[0] = loc / nb[1];
+    }
+    int kk[3];
+    for (int d = 0; d < 3; ++d) kk[d] = int(ceil(rcR * nb[d] / ci.w[d] + 1e-9));
+    const double ri[3] = {wpos[3 * i], wpos[3 * i + 1], wpos[3 * i + 2]};
     const double rc2R = rcR * rcR, rc2A = rcA * rcA;
     int cur[2 * kMaxTypes];  // FILL: write cursors {angular, radial-only} per species
     int64_t base = 0;
@@ -88,29 +227,26 @@ k_neighbors(int Ns, long Na, int T, const int64_t* __restrict__ off, const R* __
         }
     } else {
         for (int b = 0; b < 2 * T; ++b) cur[b] = 0;
-        atom_struct[i] = s;
     }
-    for (long j = j0; j < j1; ++j) {
-        const double rj[3] = {double(pos[3 * j]), double(pos[3 * j + 1]), double(pos[3 * j + 2])};
-        const int tb = types[j];
-        int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) {
-            const double fj = rj[0] * ci.Hi[d] + rj[1] * ci.Hi[3 + d] + rj[2] * ci.Hi[6 + d];
-            const double ds = fj - fi[d];
-            const double h = rcR / ci.w[d] + 1e-9;
-            lo[d] = (int)ceil(-ds - h);
-            hi[d] = (int)floor(-ds + h);
-        }
-        for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
-            for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
-                for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
-                    if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
+    for (int d0 = -kk[0]; d0 <= kk[0]; ++d0) {
+        const int t0 = c[0] + d0, m0 = floordiv(t0, nb[0]), b0 = t0 - m0 * nb[0];
+        for (int d1 = -kk[1]; d1 <= kk[1]; ++d1) {
+            const int t1 = c[1] + d1, m1 = floordiv(t1, nb[1]), b1 = t1 - m1 * nb[1];
+            for (int d2 = -kk[2]; d2 <= kk[2]; ++d2) {
+                const int t2 = c[2] + d2, m2 = floordiv(t2, nb[2]), b2 = t2 - m2 * nb[2];
+                double sh[3];
+                for (int x = 0; x < 3; ++x) sh[x] = m0 * ci.H[x] + m1 * ci.H[3 + x] + m2 * ci.H[6 + x] - ri[x];
+                const bool self_image = m0 == 0 && m1 == 0 && m2 == 0;
+                const long gb = bin_base[s] + (long(b0) * nb[1] + b1) * nb[2] + b2;
+                for (int64_t q = bin_start[gb]; q < bin_start[gb + 1]; ++q) {
+                    const int j = bin_atoms[q];
+                    if (self_image && j == i) continue;
                     double r[3];
-                    for (int d = 0; d < 3; ++d)
-                        r[d] = rj[d] + n0 * ci.H[d] + n1 * ci.H[3 + d] + n2 * ci.H[6 + d] - ri[d];
-                    const double d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                    if (!(d2 < rc2R)) continue;
-                    const bool ang = d2 < rc2A;
+                    for (int x = 0; x < 3; ++x) r[x] = wpos[3L * j + x] + sh[x];
+                    const double d2v = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                    if (!(d2v < rc2R)) continue;
+                    const bool ang = d2v < rc2A;
+                    const int tb = types[j];
                     if (FILL) {
                         const int slot = ang ? cur[2 * tb]++ : cur[2 * tb + 1]++;
                         Rec<R> rec;
@@ -118,7 +254,7 @@ k_neighbors(int Ns, long Na, int T, const int64_t* __restrict__ off, const R* __
                         rec.y = R(r[1]);
                         rec.z = R(r[2]);
                         if constexpr (sizeof(R) == 4)
-                            rec.w = __int_as_float((int)j);
+                            rec.w = __int_as_float(j);
                         else
                             rec.w = __longlong_as_double((long long)j);
                         pairs[base + slot] = rec;
@@ -127,6 +263,8 @@ k_neighbors(int Ns, long Na, int T, const int64_t* __restrict__ off, const R* __
                         if (ang) cur[2 * tb + 1] += 1;
                     }
                 }
+            }
+        }
     }
     if (!FILL) {
         int64_t tot = 0;
@@ -143,17 +281,23 @@ k_neighbors(int Ns, long Na, int T, const int64_t* __restrict__ off, const R* __
 // of row j with neighbour i whose vector is closest to -r_ij (exactly -r_ij up
 // to rounding; other images of the same atom differ by a lattice vector).
 // -1 if the reverse pair was not kept (possible only at |r_ij| = rc to rounding).
+// Only the group of row j holding neighbours of species type(i) is searched.
 template <typename R>
 __global__ void __launch_bounds__(kNbBlock)
-k_reverse(long Na, const int64_t* __restrict__ row, const Rec<R>* __restrict__ pairs, int* __restrict__ reverse) {
+k_reverse(long Na, int T, const int* __restrict__ types, const int* __restrict__ seg,
+          const int64_t* __restrict__ row, const Rec<R>* __restrict__ pairs, int* __restrict__ reverse) {
     const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
     if (i >= Na) return;
+    const int ti = types[i];
     for (int64_t p = row[i]; p < row[i + 1]; ++p) {
         const Rec<R> a = pairs[p];
         const long j = rec_j(a);
+        int64_t g0 = row[j];
+        for (int b = 0; b < ti; ++b) g0 += seg[(j * T + b) * 2];
+        const int64_t g1 = g0 + seg[(j * T + ti) * 2];
         int64_t best = -1;
         double bd = 1e300;
-        for (int64_t q = row[j]; q < row[j + 1]; ++q) {
+        for (int64_t q = g0; q < g1; ++q) {
             const Rec<R> b = pairs[q];
             if (rec_j(b) != i) continue;
             const double dx = double(a.x) + double(b.x), dy = double(a.y) + double(b.y), dz = double(a.z) + double(b.z);
@@ -169,7 +313,6 @@ k_reverse(long Na, const int64_t* __restrict__ row, const Rec<R>* __restrict__ p
 
 // Exclusive scan row[0..Na] of the per-row counts in row[1..Na] (row[0] = 0),
 // one block; also sums the angular counts into totals[1] (totals[0] = pairs).
-constexpr int kScanBlock = 1024;
 
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_rows(long Na, int T, int64_t* __restrict__ row, const int* __restrict__ seg, int64_t* __restrict__ totals) {
@@ -267,10 +410,41 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
         for (long i = 0; i < Na; ++i)
             if (typ[i] < 0 || typ[i] >= T) return fail(NEP_ERR_INVALID_ARG, "atom %ld has species %d outside [0, %d)", i, typ[i], T);
     }
+    // cell-list scratch in the workspace after the totals
+    const long max_bins = Na + Ns;
+    size_t o = 64;
+    auto carve = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return static_cast<char*>(ws) + at;
+    };
+    int* sbins = reinterpret_cast<int*>(carve(sizeof(int) * 3 * size_t(Ns)));
+    int64_t* bin_base = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (size_t(Ns) + 1)));
+    int64_t* bin_start = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (size_t(max_bins) + 1)));
+    unsigned int* cursor = reinterpret_cast<unsigned int*>(carve(sizeof(unsigned int) * size_t(max_bins)));
+    int* atom_bin = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
+    int* bin_atoms = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
+    double* wpos = reinterpret_cast<double*>(carve(sizeof(double) * 3 * size_t(Na)));
+    if (o > ws_bytes) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, the neighbour build needs %zu", ws_bytes, o);
     if (Na > 0) {
-        NEP_LAUNCH("neighbors_count", (k_neighbors<R, false>), dim3(grid), dim3(kNbBlock), 0, st, Ns, Na, T,
-                   b->atom_offset, pos, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->seg_count, nb->row_offset,
-                   nb->atom_struct, (Rec<R>*)nullptr);
+        const int sgrid = (Ns + kNbBlock - 1) / kNbBlock;
+        const int bgrid = int((max_bins + 1 + kNbBlock - 1) / kNbBlock);
+        NEP_LAUNCH("cell_setup", k_cell_setup, dim3(sgrid), dim3(kNbBlock), 0, st, Ns, b->atom_offset, b->cells,
+                   c.dm.rcR, sbins, bin_base);
+        NEP_LAUNCH("cell_scan", k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, long(Ns), bin_base);
+        NEP_LAUNCH("cell_zero", k_zero<int64_t>, dim3(bgrid), dim3(kNbBlock), 0, st, max_bins + 1, bin_start);
+        NEP_LAUNCH("cell_zero", k_zero<unsigned int>, dim3(bgrid), dim3(kNbBlock), 0, st, max_bins, cursor);
+        NEP_LAUNCH("cell_bin", (k_bin_atoms<R>), dim3(grid), dim3(kNbBlock), 0, st, Ns, Na, b->atom_offset, pos,
+                   b->cells, sbins, bin_base, nb->atom_struct, atom_bin, wpos,
+                   reinterpret_cast<unsigned long long*>(bin_start));
+        NEP_LAUNCH("cell_scan", k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, max_bins, bin_start);
+        NEP_LAUNCH("cell_fill", k_bin_fill, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, cursor,
+                   bin_atoms);
+        NEP_LAUNCH("cell_sort", k_bin_sort, dim3(bgrid), dim3(kNbBlock), 0, st, max_bins, bin_base + Ns, bin_start,
+                   bin_atoms);
+        NEP_LAUNCH("neighbors_count", (k_neighbors<R, false>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+                   b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
+                   bin_atoms, nb->seg_count, nb->row_offset, (Rec<R>*)nullptr);
     }
     NEP_LAUNCH("neighbors_scan", k_scan_rows, dim3(1), dim3(kScanBlock), 0, st, Na, T, nb->row_offset, nb->seg_count,
                totals);
@@ -287,11 +461,11 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                     (long long)host_tot[0], (long long)nb->capacity);
     }
     if (Na > 0 && host_tot[0] > 0) {
-        NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(grid), dim3(kNbBlock), 0, st, Ns, Na, T,
-                   b->atom_offset, pos, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->seg_count, nb->row_offset,
-                   nb->atom_struct, static_cast<Rec<R>*>(nb->pairs));
-        NEP_LAUNCH("neighbors_reverse", (k_reverse<R>), dim3(grid), dim3(kNbBlock), 0, st, Na, nb->row_offset,
-                   static_cast<const Rec<R>*>(nb->pairs), nb->reverse);
+        NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+                   b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
+                   bin_atoms, nb->seg_count, nb->row_offset, static_cast<Rec<R>*>(nb->pairs));
+        NEP_LAUNCH("neighbors_reverse", (k_reverse<R>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+                   nb->seg_count, nb->row_offset, static_cast<const Rec<R>*>(nb->pairs), nb->reverse);
     }
     return NEP_OK;
 }

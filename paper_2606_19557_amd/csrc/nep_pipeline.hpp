@@ -15,7 +15,7 @@ namespace nep {
 
 template <typename R, class Sh>
 nep_status run_shape(const Ctx& c) {
-    const Layout L = make_layout(c.dm, c.f64, c.Ns, c.Na, c.pairs);
+    const Layout L = make_layout(c.dm, c.plan, c.f64, c.Ns, c.Na, c.pairs);
     if (c.ws_bytes < L.total) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, %zu needed", c.ws_bytes, L.total);
     auto Wr = [&](size_t off) { return reinterpret_cast<R*>(c.ws + off); };
     auto Wd = [&](size_t off) { return reinterpret_cast<double*>(c.ws + off); };
@@ -25,14 +25,26 @@ nep_status run_shape(const Ctx& c) {
     const R* theta = static_cast<const R*>(c.theta);
     const R* qscale = static_cast<const R*>(c.qscale);
     const Rec<R>* pairs = static_cast<const Rec<R>*>(c.pair_data);
-    constexpr int S = kTeam;
-    const int team_grid = (Na + kBlock / S - 1) / (kBlock / S);
-    const int atom_grid = (Na + kBlock - 1) / kBlock;
+    auto team_grid = [&](int S) { return (Na + kBlock / S - 1) / (kBlock / S); };
+    nep_status rs = NEP_OK;
+
+    // LDS of the angular-coefficient gradient block (dynamic; <= one CU's 160 KB)
+    const size_t cg_shm = with_team_size<size_t>(c.plan.team_cg, [&](auto S_) {
+        return CoeffGradSmem<R, Sh, decltype(S_)::value>::bytes(dm.T);
+    });
+    if (c.mode == Mode::LossGrad || c.mode == Mode::Backward)
+        if (cg_shm > 160 * 1024)
+            return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block of %d-lane teams needs %zu bytes of LDS",
+                        c.plan.team_cg, cg_shm);
 
     R* q = (c.mode == Mode::Descriptors || c.desc_out) && c.desc_out ? static_cast<R*>(c.desc_out) : Wr(L.q);
-    if (Na > 0)
-        NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types,
-                   Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0));
+    if (Na > 0 && (rs = with_team(c.plan.team_desc, [&](auto S_) -> nep_status {
+            constexpr int S = decltype(S_)::value;
+            NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
+                       c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0));
+            return NEP_OK;
+        })))
+        return rs;
     if (c.mode == Mode::Descriptors) return NEP_OK;
 
     const int net_grid = int((c.Na + Mfma<R>::M - 1) / Mfma<R>::M) + dm.T;
@@ -46,13 +58,16 @@ nep_status run_shape(const Ctx& c) {
     const bool loss = c.mode == Mode::LossGrad;
 
     if (c.mode == Mode::Forward || loss) {
-        if (Na > 0)
-            NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types, Na,
-                       c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e), reinterpret_cast<Rec<R>*>(Wr(L.h)),
-                       Wr(L.Fown), Wr(L.Wat));
-        if (Na > 0)
-            NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid), dim3(kBlock), 0, st, Na, c.row,
-                       c.reverse, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
+        if (Na > 0 && (rs = with_team(c.plan.team_force, [&](auto S_) -> nep_status {
+                constexpr int S = decltype(S_)::value;
+                NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
+                           c.types, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e),
+                           reinterpret_cast<Rec<R>*>(Wr(L.h)), Wr(L.Fown), Wr(L.Wat));
+                NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, Na,
+                           c.row, c.reverse, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
+                return NEP_OK;
+            })))
+            return rs;
         if (c.Ns > 0)
             NEP_LAUNCH("structure", (k_structure<R>), dim3(c.Ns), dim3(kRedBlock), 0, st, c.Ns, c.Na, c.atom_offset,
                        Wr(L.Eat), Wr(L.Wat), F, loss ? 1 : 0, c.Et, static_cast<const R*>(c.Ft), c.Wt, c.has_v,
@@ -66,20 +81,28 @@ nep_status run_shape(const Ctx& c) {
     }
 
     if (Na > 0) {
-        NEP_LAUNCH("tangent", (k_tangent<R, Sh, S>), dim3(team_grid), dim3(kBlock), 0, st, dm, theta, c.types,
-                   c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dq), Wr(L.dA),
-                   Wr(L.S1));
+        if ((rs = with_team(c.plan.team_tangent, [&](auto S_) -> nep_status {
+                constexpr int S = decltype(S_)::value;
+                NEP_LAUNCH("tangent", (k_tangent<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
+                           c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A),
+                           Wr(L.dq), Wr(L.dA), Wr(L.S1));
+                return NEP_OK;
+            })))
+            return rs;
         NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
                    qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e), Wr(L.t),
                    Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
-        using CG = CoeffGradSmem<R, Sh, S>;
-        const size_t shm = CG::bytes(dm.T);
-        if (shm > 64 * 1024)
-            NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad<R, Sh, S>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
-        NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad<R, Sh, S>), dim3(L.ang_rows), dim3(kBlock), shm, st,
-                   dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dA),
-                   Wr(L.e), Wr(L.abar), Wd(L.ang_part));
+        if ((rs = with_team(c.plan.team_cg, [&](auto S_) -> nep_status {
+                constexpr int S = decltype(S_)::value;
+                if (cg_shm > 64 * 1024)
+                    NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad<R, Sh, S>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(cg_shm)));
+                NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad<R, Sh, S>), dim3(L.ang_rows), dim3(kBlock),
+                           cg_shm, st, dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
+                           Wr(L.A), Wr(L.dA), Wr(L.e), Wr(L.abar), Wd(L.ang_part));
+                return NEP_OK;
+            })))
+            return rs;
         NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), 0, st, dm, qscale,
                    c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha),
                    Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));

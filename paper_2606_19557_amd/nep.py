@@ -21,8 +21,8 @@ NEP_OK, NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED, NEP_ERR_CAPACITY, NEP_ERR_WORK
 NEP_F32, NEP_F64 = 0, 1
 
 EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_forward", "nep_loss_and_grad",
-           "nep_backward", "nep_adam_step", "nep_descriptor_scale", "nep_last_error", "nep_profile_enable",
-           "nep_profile_read")
+           "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale", "nep_last_error",
+           "nep_profile_enable", "nep_profile_read")
 
 
 class NepError(RuntimeError):
@@ -31,11 +31,17 @@ class NepError(RuntimeError):
         self.code = code
 
 
+class c_plan(C.Structure):
+    _fields_ = [("team_descriptor", C.c_int32), ("team_force", C.c_int32), ("team_tangent", C.c_int32),
+                ("team_coeff_grad", C.c_int32), ("coeff_grad_blocks", C.c_int32), ("outer_chunk", C.c_int32)]
+
+
 class c_model(C.Structure):
     _fields_ = [("num_types", C.c_int32), ("n_max_r", C.c_int32), ("n_max_a", C.c_int32),
                 ("basis_r", C.c_int32), ("basis_a", C.c_int32), ("l_max", C.c_int32),
                 ("l_max_4b", C.c_int32), ("l_max_5b", C.c_int32), ("hidden", C.c_int32),
-                ("dtype", C.c_int32), ("rc_r", C.c_double), ("rc_a", C.c_double)]
+                ("dtype", C.c_int32), ("rc_r", C.c_double), ("rc_a", C.c_double),
+                ("plan", C.POINTER(c_plan))]
 
 
 class c_batch(C.Structure):
@@ -82,6 +88,8 @@ def lib():
                                         C.POINTER(c_targets), vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.nep_backward.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors), vp, vp,
                                    vp, vp, vp, C.c_size_t, vp]
+        L.nep_autotune.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
+                                   C.POINTER(c_targets), vp, vp, vp, C.c_size_t, i32, C.POINTER(c_plan), vp]
         L.nep_adam_step.argtypes = [i64, i32, vp, vp, vp, vp, vp, i64, C.POINTER(c_adam), vp]
         L.nep_descriptor_scale.argtypes = [i64, i64, i32, vp, vp, vp]
         L.nep_last_error.restype = C.c_char_p
@@ -110,6 +118,24 @@ def _stream():
 
 
 @dataclass(frozen=True)
+class Plan:
+    """Launch plan (nep_plan); 0 = the library default."""
+    team_descriptor: int = 0
+    team_force: int = 0
+    team_tangent: int = 0
+    team_coeff_grad: int = 0
+    coeff_grad_blocks: int = 0
+    outer_chunk: int = 0
+
+    def c(self) -> c_plan:
+        return c_plan(self.team_descriptor, self.team_force, self.team_tangent, self.team_coeff_grad,
+                      self.coeff_grad_blocks, self.outer_chunk)
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k in self.__dataclass_fields__}
+
+
+@dataclass(frozen=True)
 class Model:
     num_types: int
     rc_r: float
@@ -123,15 +149,23 @@ class Model:
     l_max_5b: int = 0
     hidden: int = 30
     dtype: str = "f32"
+    plan: Plan | None = None
 
     @property
     def torch_dtype(self):
         return torch.float64 if self.dtype == "f64" else torch.float32
 
+    def with_plan(self, plan: Plan | None) -> "Model":
+        from dataclasses import replace
+
+        return replace(self, plan=plan)
+
     def c(self) -> c_model:
+        # the pointer object keeps the plan struct alive as long as the model struct
+        plan = C.pointer(self.plan.c()) if self.plan is not None else C.POINTER(c_plan)()
         return c_model(self.num_types, self.n_max_r, self.n_max_a, self.basis_r, self.basis_a, self.l_max,
                        self.l_max_4b, self.l_max_5b, self.hidden, NEP_F64 if self.dtype == "f64" else NEP_F32,
-                       float(self.rc_r), float(self.rc_a))
+                       float(self.rc_r), float(self.rc_a), plan)
 
     @classmethod
     def from_dict(cls, d: dict, dtype: str = "f32") -> "Model":
@@ -317,6 +351,27 @@ def nep_backward(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, dE=
     _check(lib().nep_backward(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), _ptr(dE), _ptr(dF),
                               _ptr(dW), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
     return grad
+
+
+def nep_autotune(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, targets: Targets, ws=None,
+                 repeats: int = 5) -> Plan:
+    """Time candidate launch plans on this batch (see nep.h) and return the fastest."""
+    dev, dt = batch.positions.device, model.torch_dtype
+    P, _ = nep_param_count(model)
+    if ws is None:
+        # room for the largest candidate (more partial rows than the default)
+        big = model.with_plan(Plan(4, 4, 4, 4, 4096, 32))
+        n = max(nep_workspace_size(model, batch.num_structures, batch.num_atoms, max(nbr.num_pairs, 0)),
+                nep_workspace_size(big, batch.num_structures, batch.num_atoms, max(nbr.num_pairs, 0)))
+        ws = torch.empty(n, dtype=torch.uint8, device=dev)
+    grad = torch.empty(P, dtype=dt, device=dev)
+    loss = torch.empty(4, dtype=torch.float64, device=dev)
+    out = c_plan()
+    m, b, cn, tg = model.c(), batch.c(), nbr.c(), targets.c()
+    _check(lib().nep_autotune(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), C.byref(tg),
+                              _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), int(repeats), C.byref(out), _stream()))
+    return Plan(out.team_descriptor, out.team_force, out.team_tangent, out.team_coeff_grad, out.coeff_grad_blocks,
+                out.outer_chunk)
 
 
 @dataclass

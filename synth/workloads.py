@@ -31,6 +31,15 @@ class Workload:
     dtype: str  # "f64" or "f32": bulk precision of the GPU path
     model: dict = field(default_factory=dict)
     lambdas: tuple = (1.0, 1.0, 0.1)
+    about: str = ""
+
+    @property
+    def description(self) -> str:
+        m = self.model
+        extra = (" + 4-body" if m["l_max_4b"] == 2 else "") + (" + 5-body" if m["l_max_5b"] == 1 else "")
+        return (f"{self.about}; {m['num_types']} species, rc {m['rc_r']:g}/{m['rc_a']:g} A, "
+                f"n_max {m['n_max_r']}/{m['n_max_a']}, basis {m['basis_r']}/{m['basis_a']}, "
+                f"l_max {m['l_max']}{extra}, {m['hidden']} hidden, {self.dtype}")
 
 
 def _model(T, rc_r, rc_a, n_r, n_a, b_r, b_a, l_max, l4, l5, hidden):
@@ -42,19 +51,24 @@ def _model(T, rc_r, rc_a, n_r, n_a, b_r, b_a, l_max, l4, l5, hidden):
 WORKLOADS = {
     # 8 single-element 64-atom bcc cells (4x4x2 conventional cells), FP64.
     "bcc64x8": Workload("bcc64x8", 1, 8, "f64",
-                        _model(1, 5.0, 4.0, 4, 4, 8, 8, 4, 0, 0, 30)),
+                        _model(1, 5.0, 4.0, 4, 4, 8, 8, 4, 0, 0, 30),
+                        about="8 bcc cells of 64 atoms"),
     # 256 single-element fcc cells with 32..256 atoms, strain and noise, FP32.
     "fcc_uneven_256": Workload("fcc_uneven_256", 2, 256, "f32",
-                               _model(1, 6.0, 4.0, 6, 4, 8, 8, 4, 0, 0, 30)),
+                               _model(1, 6.0, 4.0, 6, 4, 8, 8, 4, 0, 0, 30),
+                               about="256 fcc cells of 32-256 atoms"),
     # 1024 four-species fcc/bcc alloys with 16..512 atoms, 4-body and 5-body terms.
     "alloy4_1024": Workload("alloy4_1024", 3, 1024, "f32",
-                            _model(4, 6.0, 4.0, 8, 6, 12, 10, 4, 2, 1, 50)),
+                            _model(4, 6.0, 4.0, 8, 6, 12, 10, 4, 2, 1, 50),
+                            about="1024 fcc/bcc alloy cells of 16-512 atoms"),
     # 4096 three-species cells, half crystalline and half liquid-like packings.
     "mixed3_4096": Workload("mixed3_4096", 4, 4096, "f32",
-                            _model(3, 6.0, 4.0, 8, 8, 12, 12, 4, 0, 0, 80)),
+                            _model(3, 6.0, 4.0, 8, 8, 12, 12, 4, 0, 0, 80),
+                            about="4096 crystalline and liquid-like cells of 32-256 atoms"),
     # 32 five-species cells with 4000..16000 atoms (alloy and dense liquid).
     "large5_32": Workload("large5_32", 5, 32, "f32",
-                          _model(5, 6.0, 5.0, 10, 8, 12, 12, 4, 0, 0, 100)),
+                          _model(5, 6.0, 5.0, 10, 8, 12, 12, 4, 0, 0, 100),
+                          about="32 alloy and dense-liquid cells of 4000-16000 atoms"),
 }
 
 

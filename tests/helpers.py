@@ -2,6 +2,8 @@
 
 from __future__ import annotations
 
+from dataclasses import replace
+
 import numpy as np
 
 import oracle as O
@@ -48,6 +50,19 @@ def fixture(name_or_model, indices=None, seed=0, batch=None, T=None):
     teacher = draw_theta(P, base + 2000)
     Et, Ft, Wt = O.forward(m, teacher, s, batch)
     return md, m, batch, theta, s, (Et, Ft, Wt)
+
+
+def device_inputs(dtype, batch, theta, scale, targets=None):
+    """The inputs exactly as a device run in `dtype` receives them. For FP32 the
+    positions, parameters, scaler and force targets are rounded to float32 (cells,
+    energies and virials stay FP64, as in the C ABI), so the oracle and the HIP path
+    are compared on bit-identical inputs and the tolerance measures arithmetic only."""
+    if dtype != "f32":
+        return batch, theta, scale, targets
+    r = lambda x: np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    b = replace(batch, positions=r(batch.positions))
+    tg = None if targets is None else (targets[0], r(targets[1]), targets[2])
+    return b, r(theta), r(scale), tg
 
 
 def small_alloy_batch(seed=5, n_struct=5):

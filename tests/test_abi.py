@@ -94,3 +94,21 @@ def test_calls_validate_before_launching():
     cfg = nep.AdamConfig().c()
     assert L.nep_adam_step(10, 0, None, None, None, None, None, 0, C.byref(cfg), None) == nep.NEP_ERR_INVALID_ARG
     assert L.nep_adam_step(0, 0, None, None, None, None, None, 1, C.byref(cfg), None) == nep.NEP_OK
+
+
+def test_plan_validation_and_workspace():
+    """Launch plans: zero fields mean defaults, out-of-range values are rejected on the
+    host, and the workspace follows the plan's partial-row counts."""
+    _lib_or_skip()
+    m = nep.Model(num_types=2, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30)
+    base = nep.nep_workspace_size(m, 10, 5000, 200000)
+    assert nep.nep_workspace_size(m.with_plan(nep.Plan()), 10, 5000, 200000) == base
+    assert nep.nep_workspace_size(m.with_plan(nep.Plan(8, 8, 8, 8, 2048, 64)), 10, 5000, 200000) == base
+    small = nep.nep_workspace_size(m.with_plan(nep.Plan(outer_chunk=256, coeff_grad_blocks=64)), 10, 5000, 200000)
+    big = nep.nep_workspace_size(m.with_plan(nep.Plan(outer_chunk=8)), 10, 5000, 200000)
+    assert small < base < big
+    for bad in (nep.Plan(team_descriptor=5), nep.Plan(team_force=32), nep.Plan(coeff_grad_blocks=-1),
+                nep.Plan(outer_chunk=4), nep.Plan(outer_chunk=5000)):
+        with pytest.raises(nep.NepError) as e:
+            nep.nep_workspace_size(m.with_plan(bad), 10, 5000, 200000)
+        assert e.value.code == nep.NEP_ERR_INVALID_ARG

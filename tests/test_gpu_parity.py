@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle as O
-from helpers import SMALL_ALLOY, fixture, rel_err, small_alloy_batch
+from helpers import SMALL_ALLOY, device_inputs, fixture, rel_err, small_alloy_batch
 from synth import structures as S
 
 pytestmark = pytest.mark.gpu
@@ -24,6 +24,13 @@ CASES = [
     ("fcc_uneven_256", list(range(12)), "f64"),
     ("small_alloy", None, "f64"),
     ("small_alloy", None, "f32"),
+    # subsets of the larger workloads, in their own kernel shapes: 4 species with
+    # 4-body and 5-body terms; 3 species with liquid-like packings; 5 species
+    # with ~100 neighbours per atom (the smallest 4250-atom cell)
+    ("alloy4_1024", [4, 0, 1, 3], "f32"),
+    ("alloy4_1024", [4, 0, 1, 3], "f64"),
+    ("mixed3_4096", [0, 1, 2, 4, 5], "f32"),
+    ("large5_32", [20], "f32"),
 ]
 
 
@@ -32,6 +39,7 @@ def _setup(name, idx, dtype):
         md, m, b, th, s, tg = fixture(SMALL_ALLOY, seed=7, batch=small_alloy_batch())
     else:
         md, m, b, th, s, tg = fixture(name, idx)
+    b, th, s, tg = device_inputs(dtype, b, th, s, tg)
     model = N.Model.from_dict(md, dtype=dtype)
     td = model.torch_dtype
     gb = N.Batch.from_host(b, dtype=td)
