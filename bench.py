@@ -151,7 +151,7 @@ def measured_traffic(kernel, workload):
         if line.startswith("source-sha256:"):
             digest = line.split(":", 1)[1].strip()
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 6 and cells[0] == kernel:
+        if len(cells) >= 6 and cells[0] in (kernel, "k_" + kernel):
             try:
                 val = float(cells[5])
             except ValueError:

@@ -163,30 +163,26 @@ k_bin_atoms(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
 // Scatter atoms into their bins (arbitrary order within a bin, fixed below).
 __global__ void __launch_bounds__(kNbBlock)
 k_bin_fill(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
-           unsigned int* __restrict__ cursor, int* __restrict__ bin_atoms) {
+           unsigned int* __restrict__ cursor, int* __restrict__ bin_tmp) {
     const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
     if (i >= Na) return;
     const int gb = atom_bin[i];
     const unsigned int k = atomicAdd(cursor + gb, 1u);
-    bin_atoms[bin_start[gb] + k] = int(i);
+    bin_tmp[bin_start[gb] + k] = int(i);
 }
 
-// Each bin's atoms in increasing index order (insertion sort; bins are small).
+// Each bin's atoms in increasing index order: atom i's rank in its bin is the
+// number of members with a smaller index (one lane per atom).
 __global__ void __launch_bounds__(kNbBlock)
-k_bin_sort(long max_bins, const int64_t* __restrict__ nbins_total, const int64_t* __restrict__ bin_start,
-           int* __restrict__ bin_atoms) {
-    const long b = (long)blockIdx.x * kNbBlock + threadIdx.x;
-    if (b >= max_bins || b >= *nbins_total) return;
-    const int64_t lo = bin_start[b], hi = bin_start[b + 1];
-    for (int64_t x = lo + 1; x < hi; ++x) {
-        const int v = bin_atoms[x];
-        int64_t y = x - 1;
-        while (y >= lo && bin_atoms[y] > v) {
-            bin_atoms[y + 1] = bin_atoms[y];
-            --y;
-        }
-        bin_atoms[y + 1] = v;
-    }
+k_bin_rank(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
+           const int* __restrict__ bin_tmp, int* __restrict__ bin_atoms) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i >= Na) return;
+    const int gb = atom_bin[i];
+    const int64_t lo = bin_start[gb], hi = bin_start[gb + 1];
+    int64_t rank = 0;
+    for (int64_t q = lo; q < hi; ++q) rank += bin_tmp[q] < i;
+    bin_atoms[lo + rank] = int(i);
 }
 
 __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
@@ -281,34 +277,42 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
 // of row j with neighbour i whose vector is closest to -r_ij (exactly -r_ij up
 // to rounding; other images of the same atom differ by a lattice vector).
 // -1 if the reverse pair was not kept (possible only at |r_ij| = rc to rounding).
-// Only the group of row j holding neighbours of species type(i) is searched.
+// One lane per pair; the owning row is found by bisection of the row offsets
+// and only the group of row j holding neighbours of species type(i) is searched.
 template <typename R>
 __global__ void __launch_bounds__(kNbBlock)
-k_reverse(long Na, int T, const int* __restrict__ types, const int* __restrict__ seg,
+k_reverse(long Na, long npairs, int T, const int* __restrict__ types, const int* __restrict__ seg,
           const int64_t* __restrict__ row, const Rec<R>* __restrict__ pairs, int* __restrict__ reverse) {
-    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
-    if (i >= Na) return;
-    const int ti = types[i];
-    for (int64_t p = row[i]; p < row[i + 1]; ++p) {
-        const Rec<R> a = pairs[p];
-        const long j = rec_j(a);
-        int64_t g0 = row[j];
-        for (int b = 0; b < ti; ++b) g0 += seg[(j * T + b) * 2];
-        const int64_t g1 = g0 + seg[(j * T + ti) * 2];
-        int64_t best = -1;
-        double bd = 1e300;
-        for (int64_t q = g0; q < g1; ++q) {
-            const Rec<R> b = pairs[q];
-            if (rec_j(b) != i) continue;
-            const double dx = double(a.x) + double(b.x), dy = double(a.y) + double(b.y), dz = double(a.z) + double(b.z);
-            const double d = dx * dx + dy * dy + dz * dz;
-            if (d < bd) {
-                bd = d;
-                best = q;
-            }
-        }
-        reverse[p] = (best >= 0 && bd < 1e-6) ? int(best) : -1;
+    const long p = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (p >= npairs) return;
+    long lo = 0, hi = Na;  // row[lo] <= p < row[hi]
+    while (hi - lo > 1) {
+        const long mid = (lo + hi) >> 1;
+        if (row[mid] <= p)
+            lo = mid;
+        else
+            hi = mid;
     }
+    const long i = lo;
+    const int ti = types[i];
+    const Rec<R> a = pairs[p];
+    const long j = rec_j(a);
+    int64_t g0 = row[j];
+    for (int b = 0; b < ti; ++b) g0 += seg[(j * T + b) * 2];
+    const int64_t g1 = g0 + seg[(j * T + ti) * 2];
+    int64_t best = -1;
+    double bd = 1e300;
+    for (int64_t q = g0; q < g1; ++q) {
+        const Rec<R> b = pairs[q];
+        if (rec_j(b) != i) continue;
+        const double dx = double(a.x) + double(b.x), dy = double(a.y) + double(b.y), dz = double(a.z) + double(b.z);
+        const double d = dx * dx + dy * dy + dz * dz;
+        if (d < bd) {
+            bd = d;
+            best = q;
+        }
+    }
+    reverse[p] = (best >= 0 && bd < 1e-6) ? int(best) : -1;
 }
 
 // Exclusive scan row[0..Na] of the per-row counts in row[1..Na] (row[0] = 0),
@@ -424,6 +428,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     unsigned int* cursor = reinterpret_cast<unsigned int*>(carve(sizeof(unsigned int) * size_t(max_bins)));
     int* atom_bin = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
     int* bin_atoms = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
+    int* bin_tmp = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
     double* wpos = reinterpret_cast<double*>(carve(sizeof(double) * 3 * size_t(Na)));
     if (o > ws_bytes) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, the neighbour build needs %zu", ws_bytes, o);
     if (Na > 0) {
@@ -439,8 +444,8 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                    reinterpret_cast<unsigned long long*>(bin_start));
         NEP_LAUNCH("cell_scan", k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, max_bins, bin_start);
         NEP_LAUNCH("cell_fill", k_bin_fill, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, cursor,
-                   bin_atoms);
-        NEP_LAUNCH("cell_sort", k_bin_sort, dim3(bgrid), dim3(kNbBlock), 0, st, max_bins, bin_base + Ns, bin_start,
+                   bin_tmp);
+        NEP_LAUNCH("cell_rank", k_bin_rank, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, bin_tmp,
                    bin_atoms);
         NEP_LAUNCH("neighbors_count", (k_neighbors<R, false>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
                    b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
@@ -464,8 +469,10 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
         NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
                    b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
                    bin_atoms, nb->seg_count, nb->row_offset, static_cast<Rec<R>*>(nb->pairs));
-        NEP_LAUNCH("neighbors_reverse", (k_reverse<R>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
-                   nb->seg_count, nb->row_offset, static_cast<const Rec<R>*>(nb->pairs), nb->reverse);
+        const long np = host_tot[0];
+        NEP_LAUNCH("neighbors_reverse", (k_reverse<R>), dim3(int((np + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
+                   st, Na, np, T, b->types, nb->seg_count, nb->row_offset, static_cast<const Rec<R>*>(nb->pairs),
+                   nb->reverse);
     }
     return NEP_OK;
 }
