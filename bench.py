@@ -37,13 +37,15 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--steps", type=int, default=None,
+                   help="timed steps (default 50; a whole epoch of minibatches for a minibatch workload)")
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--workload", default="fcc_uneven_256")
     p.add_argument("--profile-steps", type=int, default=5)
     p.add_argument("--comparator-steps", type=int, default=3)
     p.add_argument("--no-comparator", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-autotune", action="store_true", help="use the default launch plan")
     p.add_argument("--cpu-structures", type=int, default=256)
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="repeat the oracle over the sample until this much time has passed")
@@ -204,6 +206,43 @@ def main():
     qs = N.nep_descriptor_scale(q)
     Et, Ft, Wt = N.nep_forward(model, teacher, qs, gb, nb, ws)
     targets = N.Targets(Et, Ft, Wt, lambdas=w.lambdas, dtype=td, device=dev)
+    epoch_mode = w.minibatch > 0
+    if epoch_mode:
+        # a training epoch: shuffled minibatches packed on the device from the
+        # dataset's lists (built once), one Adam step each
+        from paper_2606_19557_amd.train import Dataset
+
+        data = Dataset.from_device(model, gb, nb, targets, host.atom_offset)
+        order = np.random.Generator(np.random.PCG64(w.seed + 4000)).permutation(host.num_structures)
+        mbs = [order[lo:lo + w.minibatch] for lo in range(0, len(order), w.minibatch)]
+        sizes = np.array([data.sizes(ids) for ids in mbs])
+        tune_b, tune_nb, tune_tg = data.minibatch(mbs[0])
+        log(f"epoch of {len(mbs)} minibatches of {w.minibatch}: mean {sizes[:, 0].mean():.0f} atoms, "
+            f"{sizes[:, 1].mean():.0f} pairs")
+    else:
+        tune_b, tune_nb, tune_tg = gb, nb, targets
+    plan = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        plan = N.nep_autotune(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3)
+        model = model.with_plan(plan)
+        log(f"autotuned plan in {time.perf_counter() - t0:.2f} s: {plan.as_dict()}")
+    if epoch_mode:
+        data.model = model
+        big = int(np.argmax(sizes[:, 1]))
+        ws = torch.empty(max(256, N.nep_workspace_size(model, w.minibatch, int(sizes[:, 0].max()),
+                                                       int(sizes[:, 1].max()))), dtype=torch.uint8, device=dev)
+        structs_per_step = w.minibatch
+        counts = {"pairs": float(sizes[:, 1].mean()), "angular_pairs": float(sizes[:, 2].mean()),
+                  "atoms": float(sizes[:, 0].mean()), "structures": w.minibatch, "real_bytes": 8 if w.dtype == "f64" else 4}
+        del big
+    else:
+        ws = N.workspace(model, gb, nb)
+        structs_per_step = host.num_structures
+        counts = {"pairs": nb.num_pairs, "angular_pairs": nb.num_angular_pairs, "atoms": host.num_atoms,
+                  "structures": host.num_structures, "real_bytes": 8 if w.dtype == "f64" else 4}
+    if args.steps is None:
+        args.steps = len(mbs) if epoch_mode else 50
     m_ = torch.zeros(P, dtype=td, device=dev)
     v_ = torch.zeros(P, dtype=td, device=dev)
     vm_ = torch.zeros(P, dtype=td, device=dev)
@@ -214,7 +253,11 @@ def main():
     step_no = [0]
 
     def step():
-        N.nep_loss_and_grad(model, th, qs, gb, nb, targets, ws, grad=grad, loss=loss)
+        if epoch_mode:
+            b_, nb_, tg_ = data.minibatch(mbs[step_no[0] % len(mbs)])
+        else:
+            b_, nb_, tg_ = gb, nb, targets
+        N.nep_loss_and_grad(model, th, qs, b_, nb_, tg_, ws, grad=grad, loss=loss)
         step_no[0] += 1
         N.nep_adam_step(th, grad, m_, v_, vm_, step_no[0], adam)
 
@@ -230,7 +273,7 @@ def main():
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / args.steps
-    sps = host.num_structures / (ms * 1e-3)
+    sps = structs_per_step / (ms * 1e-3)
     log(f"timed {args.steps} steps: {ms:.4f} ms/step, {sps:.1f} structures/s, loss {loss[0].item():.6e}")
 
     if args.copy_calibration > 0:
@@ -255,8 +298,6 @@ def main():
         log(f"  kernel {name:22s} launches {n:4d}  avg {tot / n * 1e3:9.2f} us")
     dom = max(rows, key=lambda r: r[2] * (r[1] / args.profile_steps))
     name, n, avg_ms = dom
-    counts = {"pairs": nb.num_pairs, "angular_pairs": nb.num_angular_pairs, "atoms": host.num_atoms,
-              "structures": host.num_structures, "real_bytes": 8 if w.dtype == "f64" else 4}
     work = work_model(name, w.model, counts)
     peak_alu = PEAK_FP64_TFLOPS if w.dtype == "f64" else PEAK_FP32_TFLOPS
     roof = None
@@ -286,23 +327,26 @@ def main():
         from comparator import AutogradNEP, pairs_from_csr
 
         try:
-            pi, pj, pr = pairs_from_csr(nb.row_offset[: host.num_atoms + 1], nb.neighbor_index().to(dev),
-                                        nb.pairs[: nb.num_pairs, :3])
-            net = AutogradNEP(w.model, gb.types, gb.atom_offset, pi, pj, pr.to(td))
-            Ft_c = targets.force
+            # the timed batch (the first minibatch of the epoch in epoch mode)
+            cb, cnb, ctg = tune_b, tune_nb, tune_tg
+            pi, pj, pr = pairs_from_csr(cnb.row_offset[: cb.num_atoms + 1], cnb.neighbor_index().to(dev),
+                                        cnb.pairs[: cnb.num_pairs, :3])
+            net = AutogradNEP(w.model, cb.types, cb.atom_offset, pi, pj, pr.to(td))
+            Ft_c = ctg.force
             for _ in range(1):
-                net.loss_and_grad(th, qs, targets.energy.to(td), Ft_c, targets.virial.to(td), w.lambdas)
+                net.loss_and_grad(th, qs, ctg.energy.to(td), Ft_c, ctg.virial.to(td), w.lambdas)
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             for _ in range(args.comparator_steps):
-                parts, gc = net.loss_and_grad(th, qs, targets.energy.to(td), Ft_c, targets.virial.to(td), w.lambdas)
+                parts, gc = net.loss_and_grad(th, qs, ctg.energy.to(td), Ft_c, ctg.virial.to(td), w.lambdas)
             b.record()
             torch.cuda.synchronize()
             cms = a.elapsed_time(b) / args.comparator_steps
-            N.nep_loss_and_grad(model, th, qs, gb, nb, targets, ws, grad=grad, loss=loss)
+            wsc = N.workspace(model, cb, cnb)
+            N.nep_loss_and_grad(model, th, qs, cb, cnb, ctg, wsc, grad=grad, loss=loss)
             rel = float((gc - grad).abs().max() / grad.abs().max())
-            comp = {"kind": "torch autograd double backward", "value": round(host.num_structures / (cms * 1e-3), 1),
+            comp = {"kind": "torch autograd double backward", "value": round(cb.num_structures / (cms * 1e-3), 1),
                     "unit": "structures/s", "ms_per_step": round(cms, 3), "speedup": round(cms / ms, 2),
                     "grad_max_rel_diff": rel}
             log(f"comparator {cms:.3f} ms/step -> speedup {cms / ms:.2f}x (grad rel diff {rel:.2e})")
@@ -353,7 +397,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w.description}",
                    "structures": host.num_structures, "atoms": host.num_atoms, "pairs": nb.num_pairs,
-                   "angular_pairs": nb.num_angular_pairs, "parallelism": "single GPU"},
+                   "angular_pairs": nb.num_angular_pairs, "parallelism": "single GPU",
+                   "plan": None if plan is None else plan.as_dict(),
+                   **({"minibatch": w.minibatch, "steps_per_epoch": len(mbs),
+                       "epoch_s": round(ms * len(mbs) * 1e-3, 5)} if epoch_mode else {})},
         "roofline": roof,
         "cpu_baseline": cpu,
         "autograd_comparator": comp,

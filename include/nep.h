@@ -161,6 +161,28 @@ nep_status nep_workspace_size(const nep_model* model, int32_t num_structures, in
 nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, nep_neighbors* nbr, void* ws,
                                size_t ws_bytes, void* stream);
 
+/* Data loader of a training epoch (mini-batch training, Methods): copies the
+ * structures ids[0..num_ids) of a packed dataset `src`, with their neighbour
+ * lists (built once for the dataset) and targets, into a packed minibatch, in
+ * the order given. Atoms, neighbour indices j and reverse-pair indices are
+ * renumbered; the minibatch's species order is recomputed; energies, virials
+ * and has_virial (1 when the dataset has no mask) follow their structures.
+ * ids is a device array; an id outside [0, src Ns) selects an empty structure.
+ * The caller allocates the minibatch arrays: atom_offset [num_ids+1], cells
+ * [num_ids][3][3], positions/force [num_atoms][3], types [num_atoms], and nbr
+ * (row_offset [num_atoms+1], seg_count, atom_struct, species_order, species_offset,
+ * pairs/reverse of nbr->capacity), where num_atoms and the pair count are the
+ * sums of the selected structures' counts (kept by the caller on the host);
+ * nbr->num_pairs and num_angular_pairs are left to the caller. Sizes that do
+ * not match give wrong lists but no access outside the given arrays.
+ * src_targets may be NULL (then energy, force, virial are not written); any of
+ * energy, force, virial, has_virial may be NULL. ws: 8 (num_ids + 1) bytes. */
+nep_status nep_gather_batch(const nep_model* model, const nep_batch* src, const nep_neighbors* src_nbr,
+                            const nep_targets* src_targets, const int32_t* ids, int32_t num_ids, int64_t num_atoms,
+                            int64_t* atom_offset, void* positions, int32_t* types, double* cells, nep_neighbors* nbr,
+                            double* energy, void* force, double* virial, uint8_t* has_virial, void* ws,
+                            size_t ws_bytes, void* stream);
+
 /* Energies E_s = sum_i E_i (Eq. 1), forces F_k = -dE/dr_k and virials
  * W_s = -sum_{i in s, j} r_ij (x) dE_i/dr_ij (9 components, row-major).
  *   theta   [P] dtype; q_scale [D] dtype (Eq. 2 factors 1/(q_max - q_min));

@@ -17,6 +17,7 @@ from .nep import (  # noqa: F401
     nep_descriptor_scale,
     nep_descriptors,
     nep_forward,
+    nep_gather_batch,
     nep_loss_and_grad,
     nep_param_count,
     nep_profile_enable,

@@ -336,6 +336,39 @@ nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, n
     return build_neighbors(c, batch, nbr, ws, ws_bytes);
 }
 
+nep_status nep_gather_batch(const nep_model* model, const nep_batch* src, const nep_neighbors* src_nbr,
+                            const nep_targets* src_targets, const int32_t* ids, int32_t num_ids, int64_t num_atoms,
+                            int64_t* atom_offset, void* positions, int32_t* types, double* cells, nep_neighbors* nbr,
+                            double* energy, void* force, double* virial, uint8_t* has_virial, void* ws,
+                            size_t ws_bytes, void* stream) {
+    clear_error();
+    Ctx c;
+    std::memset(&c, 0, sizeof(c));
+    nep_status s;
+    if ((s = make_dims(model, &c.dm))) return s;
+    if ((s = check_batch(src))) return s;
+    if ((s = check_nbr(src_nbr, src))) return s;
+    if (num_ids < 0 || num_atoms < 0) return fail(NEP_ERR_INVALID_ARG, "negative minibatch sizes");
+    if (num_ids > 0 && (!ids || !atom_offset || !cells)) return fail(NEP_ERR_INVALID_ARG, "NULL minibatch array");
+    if (!atom_offset) return fail(NEP_ERR_INVALID_ARG, "atom_offset is NULL");
+    if (num_atoms > 0 && (!positions || !types)) return fail(NEP_ERR_INVALID_ARG, "NULL minibatch atom array");
+    if (!nbr || !nbr->row_offset || !nbr->species_offset ||
+        (num_atoms > 0 && (!nbr->seg_count || !nbr->atom_struct || !nbr->species_order)))
+        return fail(NEP_ERR_INVALID_ARG, "a minibatch neighbour array is NULL");
+    if (nbr->capacity < 0 || (nbr->capacity > 0 && (!nbr->pairs || !nbr->reverse)))
+        return fail(NEP_ERR_INVALID_ARG, "bad minibatch pair capacity or buffer");
+    if (src_targets && num_ids > 0 && ((energy && !src_targets->energy) || (virial && !src_targets->virial)))
+        return fail(NEP_ERR_INVALID_ARG, "target energy/virial requested but absent in the dataset");
+    if (src_targets && num_atoms > 0 && force && !src_targets->force)
+        return fail(NEP_ERR_INVALID_ARG, "target force requested but absent in the dataset");
+    if (!ws) return fail(NEP_ERR_INVALID_ARG, "workspace is NULL");
+    c.f64 = model->dtype == NEP_F64;
+    c.stream = static_cast<hipStream_t>(stream);
+    return gather_batch(c, src, src_nbr, src_targets, ids, num_ids, long(num_atoms), atom_offset, positions, types,
+                        cells, nbr, src_targets ? energy : nullptr, src_targets ? force : nullptr,
+                        src_targets ? virial : nullptr, has_virial, ws, ws_bytes);
+}
+
 nep_status nep_forward(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
                        const nep_neighbors* nbr, double* energy, void* force, double* virial, void* descriptor,
                        void* ws, size_t ws_bytes, void* stream) {

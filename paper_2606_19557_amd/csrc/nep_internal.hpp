@@ -137,5 +137,9 @@ const ShapeEntry* find_shape(const Dims& dm);
 const ShapeEntry* shape_table(int* count);
 
 nep_status build_neighbors(const Ctx& c, const nep_batch* b, nep_neighbors* nb, void* ws, size_t ws_bytes);
+nep_status gather_batch(const Ctx& c, const nep_batch* src, const nep_neighbors* sn, const nep_targets* st,
+                        const int* ids, int n, long Na, int64_t* dst_off, void* dst_pos, int* dst_types,
+                        double* dst_cells, nep_neighbors* dn, double* dst_E, void* dst_F, double* dst_W,
+                        uint8_t* dst_hv, void* ws, size_t ws_bytes);
 
 }  // namespace nep

@@ -391,6 +391,177 @@ k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ 
     if (threadIdx.x <= (unsigned)T) soff[threadIdx.x] = tot_s[threadIdx.x];
 }
 
+// ------------------------------------------------------------- minibatches
+
+// Per selected structure k (one block, chunked scan): atom and pair counts of
+// structure ids[k] -> minibatch atom offsets and pair bases; per-structure
+// cells and targets. ids outside [0, Ns) select an empty structure.
+__global__ void __launch_bounds__(kScanBlock)
+k_gather_structs(int n, const int* __restrict__ ids, int Ns, const int64_t* __restrict__ src_off,
+                 const int64_t* __restrict__ src_row, const double* __restrict__ src_cells,
+                 const double* __restrict__ src_E, const double* __restrict__ src_W, const uint8_t* __restrict__ src_hv,
+                 int64_t* __restrict__ dst_off, int64_t* __restrict__ pair_base, double* __restrict__ dst_cells,
+                 double* __restrict__ dst_E, double* __restrict__ dst_W, uint8_t* __restrict__ dst_hv) {
+    __shared__ int64_t ba[kScanBlock], bp[kScanBlock];
+    __shared__ int64_t carry_a, carry_p;
+    if (threadIdx.x == 0) {
+        carry_a = carry_p = 0;
+        dst_off[0] = 0;
+        pair_base[0] = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < n; base += kScanBlock) {
+        const int k = base + threadIdx.x;
+        int64_t ca = 0, cp = 0;
+        if (k < n) {
+            const int sid = ids[k];
+            if (sid >= 0 && sid < Ns) {
+                ca = src_off[sid + 1] - src_off[sid];
+                cp = src_row[src_off[sid + 1]] - src_row[src_off[sid]];
+                for (int x = 0; x < 9; ++x) dst_cells[9L * k + x] = src_cells[9L * sid + x];
+                if (dst_E && src_E) dst_E[k] = src_E[sid];
+                if (dst_W && src_W)
+                    for (int x = 0; x < 9; ++x) dst_W[9L * k + x] = src_W[9L * sid + x];
+                if (dst_hv) dst_hv[k] = src_hv ? src_hv[sid] : uint8_t(1);
+            } else {
+                for (int x = 0; x < 9; ++x) dst_cells[9L * k + x] = x % 4 == 0 ? 1.0 : 0.0;
+                if (dst_E) dst_E[k] = 0.0;
+                if (dst_W)
+                    for (int x = 0; x < 9; ++x) dst_W[9L * k + x] = 0.0;
+                if (dst_hv) dst_hv[k] = 0;
+            }
+        }
+        ba[threadIdx.x] = ca;
+        bp[threadIdx.x] = cp;
+        __syncthreads();
+        for (int o = 1; o < kScanBlock; o <<= 1) {
+            const int64_t ta = (threadIdx.x >= (unsigned)o) ? ba[threadIdx.x - o] : 0;
+            const int64_t tp = (threadIdx.x >= (unsigned)o) ? bp[threadIdx.x - o] : 0;
+            __syncthreads();
+            ba[threadIdx.x] += ta;
+            bp[threadIdx.x] += tp;
+            __syncthreads();
+        }
+        const int64_t ia = ba[threadIdx.x] + carry_a, ip = bp[threadIdx.x] + carry_p;
+        if (k < n) {
+            dst_off[k + 1] = ia;
+            pair_base[k + 1] = ip;
+        }
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) {
+            carry_a = ia;
+            carry_p = ip;
+        }
+        __syncthreads();
+    }
+}
+
+// Per minibatch atom a < min(Na, dst_off[n]): position, species, per-species
+// pair counts, force target, structure index and row end.
+template <typename R>
+__global__ void __launch_bounds__(kNbBlock)
+k_gather_atoms(long Na, int n, int T, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
+               const int64_t* __restrict__ src_row, const R* __restrict__ src_pos, const int* __restrict__ src_types,
+               const int* __restrict__ src_seg, const R* __restrict__ src_F, const int64_t* __restrict__ dst_off,
+               const int64_t* __restrict__ pair_base, R* __restrict__ dst_pos, int* __restrict__ dst_types,
+               int* __restrict__ dst_seg, R* __restrict__ dst_F, int* __restrict__ dst_struct,
+               int64_t* __restrict__ dst_row) {
+    const long a = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (a == 0) dst_row[0] = 0;
+    if (a >= Na || a >= dst_off[n]) return;
+    int lo = 0, hi = n;  // dst_off[lo] <= a < dst_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (dst_off[mid] <= a)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int k = lo, sid = ids[k];
+    const long sa = src_off[sid] + (a - dst_off[k]);
+    for (int x = 0; x < 3; ++x) dst_pos[3 * a + x] = src_pos[3 * sa + x];
+    if (dst_F && src_F)
+        for (int x = 0; x < 3; ++x) dst_F[3 * a + x] = src_F[3 * sa + x];
+    dst_types[a] = src_types[sa];
+    for (int x = 0; x < 2 * T; ++x) dst_seg[2L * T * a + x] = src_seg[2L * T * sa + x];
+    dst_struct[a] = k;
+    dst_row[a + 1] = pair_base[k] + (src_row[sa + 1] - src_row[src_off[sid]]);
+}
+
+// Per minibatch pair p < min(P, pair_base[n]) inside the rows written above:
+// the record with j renumbered and the reverse index moved to the minibatch's
+// pair numbering.
+template <typename R>
+__global__ void __launch_bounds__(kNbBlock)
+k_gather_pairs(long P, long Na, int n, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
+               const int64_t* __restrict__ src_row, const Rec<R>* __restrict__ src_pairs,
+               const int* __restrict__ src_rev, const int64_t* __restrict__ dst_off,
+               const int64_t* __restrict__ pair_base, const int* __restrict__ dst_struct,
+               const int64_t* __restrict__ dst_row, Rec<R>* __restrict__ dst_pairs, int* __restrict__ dst_rev) {
+    const long p = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    // rows 0 .. hi-1 were written by k_gather_atoms (hi <= the caller's Na)
+    const long hi0 = Na < dst_off[n] ? Na : dst_off[n];
+    if (p >= P || p >= pair_base[n] || hi0 == 0 || p >= dst_row[hi0]) return;
+    long lo = 0, hi = hi0;  // dst_row[lo] <= p < dst_row[hi]
+    while (hi - lo > 1) {
+        const long mid = (lo + hi) >> 1;
+        if (dst_row[mid] <= p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const long a = lo;
+    const int k = dst_struct[a], sid = ids[k];
+    const long sa = src_off[sid] + (a - dst_off[k]);
+    const long sp = src_row[sa] + (p - dst_row[a]);
+    Rec<R> r = src_pairs[sp];
+    const long j = long(rec_j(r)) - src_off[sid] + dst_off[k];
+    if constexpr (sizeof(R) == 4)
+        r.w = __int_as_float(int(j));
+    else
+        r.w = __longlong_as_double((long long)j);
+    dst_pairs[p] = r;
+    const int rv = src_rev[sp];
+    dst_rev[p] = rv < 0 ? -1 : int(rv - src_row[src_off[sid]] + pair_base[k]);
+}
+
+template <typename R>
+nep_status gather_impl(const Ctx& c, const nep_batch* src, const nep_neighbors* sn, const nep_targets* st_,
+                       const int* ids, int n, long Na, int64_t* dst_off, void* dst_pos, int* dst_types,
+                       double* dst_cells, nep_neighbors* dn, double* dst_E, void* dst_F, double* dst_W,
+                       uint8_t* dst_hv, void* ws, size_t ws_bytes) {
+    const int T = c.dm.T;
+    hipStream_t st = c.stream;
+    const size_t need = sizeof(int64_t) * (size_t(n) + 1);
+    if (ws_bytes < need) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, the gather needs %zu", ws_bytes, need);
+    int64_t* pair_base = static_cast<int64_t*>(ws);
+    const double* sE = st_ ? st_->energy : nullptr;
+    const double* sW = st_ ? st_->virial : nullptr;
+    const uint8_t* sH = st_ ? st_->has_virial : nullptr;
+    const R* sF = st_ ? static_cast<const R*>(st_->force) : nullptr;
+    NEP_LAUNCH("gather_structs", k_gather_structs, dim3(1), dim3(kScanBlock), 0, st, n, ids, src->num_structures,
+               src->atom_offset, sn->row_offset, src->cells, sE, sW, sH, dst_off, pair_base, dst_cells, dst_E, dst_W,
+               dst_hv);
+    const long P = dn->capacity;
+    if (Na > 0)
+        NEP_LAUNCH("gather_atoms", (k_gather_atoms<R>), dim3(int((Na + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
+                   st, Na, n, T, ids, src->atom_offset, sn->row_offset, static_cast<const R*>(src->positions),
+                   src->types, sn->seg_count, sF, dst_off, pair_base, static_cast<R*>(dst_pos), dst_types,
+                   dn->seg_count, static_cast<R*>(dst_F), dn->atom_struct, dn->row_offset);
+    else
+        NEP_LAUNCH("gather_atoms", (k_gather_atoms<R>), dim3(1), dim3(kNbBlock), 0, st, 0L, n, T, ids,
+                   src->atom_offset, sn->row_offset, static_cast<const R*>(src->positions), src->types, sn->seg_count,
+                   sF, dst_off, pair_base, static_cast<R*>(dst_pos), dst_types, dn->seg_count, static_cast<R*>(dst_F),
+                   dn->atom_struct, dn->row_offset);
+    if (P > 0)
+        NEP_LAUNCH("gather_pairs", (k_gather_pairs<R>), dim3(int((P + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
+                   st, P, Na, n, ids, src->atom_offset, sn->row_offset, static_cast<const Rec<R>*>(sn->pairs), sn->reverse,
+                   dst_off, pair_base, dn->atom_struct, dn->row_offset, static_cast<Rec<R>*>(dn->pairs), dn->reverse);
+    NEP_LAUNCH("species_sort", k_species_sort, dim3(1), dim3(kScanBlock), 0, st, Na, T, dst_types, dn->species_order,
+               dn->species_offset);
+    return NEP_OK;
+}
+
 template <typename R>
 nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors* nb, void* ws, size_t ws_bytes) {
     const long Na = b->num_atoms;
@@ -482,6 +653,16 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
 nep_status build_neighbors(const Ctx& c, const nep_batch* b, nep_neighbors* nb, void* ws, size_t ws_bytes) {
     return c.f64 ? build_neighbors_impl<double>(c, b, nb, ws, ws_bytes)
                  : build_neighbors_impl<float>(c, b, nb, ws, ws_bytes);
+}
+
+nep_status gather_batch(const Ctx& c, const nep_batch* src, const nep_neighbors* sn, const nep_targets* st,
+                        const int* ids, int n, long Na, int64_t* dst_off, void* dst_pos, int* dst_types,
+                        double* dst_cells, nep_neighbors* dn, double* dst_E, void* dst_F, double* dst_W,
+                        uint8_t* dst_hv, void* ws, size_t ws_bytes) {
+    return c.f64 ? gather_impl<double>(c, src, sn, st, ids, n, Na, dst_off, dst_pos, dst_types, dst_cells, dn, dst_E,
+                                       dst_F, dst_W, dst_hv, ws, ws_bytes)
+                 : gather_impl<float>(c, src, sn, st, ids, n, Na, dst_off, dst_pos, dst_types, dst_cells, dn, dst_E,
+                                      dst_F, dst_W, dst_hv, ws, ws_bytes);
 }
 
 }  // namespace nep

@@ -20,9 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libnep.so")
 NEP_OK, NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED, NEP_ERR_CAPACITY, NEP_ERR_WORKSPACE, NEP_ERR_HIP = 0, -1, -2, -3, -4, -5
 NEP_F32, NEP_F64 = 0, 1
 
-EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_forward", "nep_loss_and_grad",
-           "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale", "nep_last_error",
-           "nep_profile_enable", "nep_profile_read")
+EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_gather_batch", "nep_forward",
+           "nep_loss_and_grad", "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale",
+           "nep_last_error", "nep_profile_enable", "nep_profile_read")
 
 
 class NepError(RuntimeError):
@@ -82,6 +82,9 @@ def lib():
         L.nep_workspace_size.argtypes = [C.POINTER(c_model), i32, i64, i64, C.POINTER(C.c_size_t)]
         L.nep_build_neighbors.argtypes = [C.POINTER(c_model), C.POINTER(c_batch), C.POINTER(c_neighbors), vp,
                                           C.c_size_t, vp]
+        L.nep_gather_batch.argtypes = [C.POINTER(c_model), C.POINTER(c_batch), C.POINTER(c_neighbors),
+                                       C.POINTER(c_targets), vp, i32, i64, vp, vp, vp, vp, C.POINTER(c_neighbors),
+                                       vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.nep_forward.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors), vp, vp,
                                   vp, vp, vp, C.c_size_t, vp]
         L.nep_loss_and_grad.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
@@ -194,7 +197,11 @@ class Batch:
         self.atom_offset = torch.as_tensor(atom_offset).to(device=device, dtype=torch.int64).contiguous()
         self.num_structures = int(self.cells.shape[0])
         self.num_atoms = int(self.positions.shape[0])
-        self.counts = torch.diff(self.atom_offset.cpu())
+
+    @property
+    def counts(self):
+        """Atoms per structure (host tensor; reads the offsets back)."""
+        return torch.diff(self.atom_offset.cpu())
 
     @classmethod
     def from_host(cls, b, dtype=torch.float32, device="cuda"):
@@ -209,15 +216,23 @@ class Neighbors:
     """Device-resident neighbour lists (see nep_neighbors in nep.h)."""
 
     def __init__(self, model: Model, batch: Batch, capacity: int):
-        dev = batch.positions.device
-        Na, T = batch.num_atoms, model.num_types
-        self.row_offset = torch.zeros(Na + 1, dtype=torch.int64, device=dev)
-        self.seg_count = torch.zeros((Na, T, 2), dtype=torch.int32, device=dev)
-        self.pairs = torch.zeros((max(capacity, 1), 4), dtype=model.torch_dtype, device=dev)
-        self.reverse = torch.zeros(max(capacity, 1), dtype=torch.int32, device=dev)
-        self.atom_struct = torch.zeros(max(Na, 1), dtype=torch.int32, device=dev)
-        self.species_order = torch.zeros(max(Na, 1), dtype=torch.int32, device=dev)
-        self.species_offset = torch.zeros(T + 1, dtype=torch.int64, device=dev)
+        self._alloc(model.num_types, batch.num_atoms, capacity, model.torch_dtype, batch.positions.device)
+
+    @classmethod
+    def empty(cls, num_types: int, num_atoms: int, capacity: int, dtype, device) -> "Neighbors":
+        nb = cls.__new__(cls)
+        nb._alloc(num_types, num_atoms, capacity, dtype, device, zero=False)
+        return nb
+
+    def _alloc(self, T, Na, capacity, dtype, dev, zero=True):
+        new = torch.zeros if zero else torch.empty
+        self.row_offset = new(Na + 1, dtype=torch.int64, device=dev)
+        self.seg_count = new((Na, T, 2), dtype=torch.int32, device=dev)
+        self.pairs = new((max(capacity, 1), 4), dtype=dtype, device=dev)
+        self.reverse = new(max(capacity, 1), dtype=torch.int32, device=dev)
+        self.atom_struct = new(max(Na, 1), dtype=torch.int32, device=dev)
+        self.species_order = new(max(Na, 1), dtype=torch.int32, device=dev)
+        self.species_offset = new(T + 1, dtype=torch.int64, device=dev)
         self.capacity = capacity
         self.num_pairs = -1
         self.num_angular_pairs = -1
@@ -265,6 +280,45 @@ def nep_build_neighbors(model: Model, batch: Batch, capacity: int | None = None,
         _check(code)
         return nb
     raise NepError(NEP_ERR_CAPACITY, "neighbour capacity retry failed")
+
+
+def nep_gather_batch(model: Model, src: Batch, src_nbr: Neighbors, src_targets, ids, num_atoms: int,
+                     num_pairs: int, num_angular_pairs: int, ws=None):
+    """Minibatch of structures `ids` (device int32 tensor) of a packed dataset:
+    (Batch, Neighbors, Targets or None). num_atoms / num_pairs / num_angular_pairs
+    are the sums of the selected structures' counts (see Dataset)."""
+    dev, dt = src.positions.device, model.torch_dtype
+    n = int(ids.numel())
+    ids = ids.to(device=dev, dtype=torch.int32).contiguous()
+    T = model.num_types
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    pos = torch.empty((num_atoms, 3), dtype=dt, device=dev)
+    typ = torch.empty(num_atoms, dtype=torch.int32, device=dev)
+    cells = torch.empty((n, 3, 3), dtype=torch.float64, device=dev)
+    nb = Neighbors.empty(T, num_atoms, num_pairs, dt, dev)
+    tg = None
+    E = F = W = hv = None
+    if src_targets is not None:
+        E = torch.empty(n, dtype=torch.float64, device=dev)
+        F = torch.empty((num_atoms, 3), dtype=dt, device=dev)
+        W = torch.empty((n, 9), dtype=torch.float64, device=dev)
+        hv = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = ws if ws is not None and ws.numel() >= 8 * (n + 1) else torch.empty(8 * (n + 1), dtype=torch.uint8,
+                                                                             device=dev)
+    m, sb, sn, cn = model.c(), src.c(), src_nbr.c(), nb.c()
+    stg = src_targets.c() if src_targets is not None else None
+    _check(lib().nep_gather_batch(C.byref(m), C.byref(sb), C.byref(sn), C.byref(stg) if stg is not None else None,
+                                  _ptr(ids), n, int(num_atoms), _ptr(off), _ptr(pos), _ptr(typ), _ptr(cells),
+                                  C.byref(cn), _ptr(E), _ptr(F), _ptr(W), _ptr(hv), _ptr(ws), ws.numel(), _stream()))
+    nb.num_pairs, nb.num_angular_pairs = int(num_pairs), int(num_angular_pairs)
+    b = Batch.__new__(Batch)
+    b.positions, b.types, b.cells, b.atom_offset = pos, typ, cells, off
+    b.num_structures, b.num_atoms = n, int(num_atoms)
+    if src_targets is not None:
+        tg = Targets.__new__(Targets)
+        tg.energy, tg.force, tg.virial, tg.has_virial = E, F, W, hv
+        tg.lambdas = src_targets.lambdas
+    return b, nb, tg
 
 
 # --------------------------------------------------------------- compute

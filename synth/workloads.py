@@ -32,6 +32,7 @@ class Workload:
     model: dict = field(default_factory=dict)
     lambdas: tuple = (1.0, 1.0, 0.1)
     about: str = ""
+    minibatch: int = 0  # > 0: a training epoch in minibatches of this size
 
     @property
     def description(self) -> str:
@@ -64,7 +65,8 @@ WORKLOADS = {
     # 4096 three-species cells, half crystalline and half liquid-like packings.
     "mixed3_4096": Workload("mixed3_4096", 4, 4096, "f32",
                             _model(3, 6.0, 4.0, 8, 8, 12, 12, 4, 0, 0, 80),
-                            about="4096 crystalline and liquid-like cells of 32-256 atoms"),
+                            about="4096 crystalline and liquid-like cells of 32-256 atoms, minibatch 64",
+                            minibatch=64),
     # 32 five-species cells with 4000..16000 atoms (alloy and dense liquid).
     "large5_32": Workload("large5_32", 5, 32, "f32",
                           _model(5, 6.0, 5.0, 10, 8, 12, 12, 4, 0, 0, 100),

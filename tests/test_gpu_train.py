@@ -1,0 +1,83 @@
+"""Minibatch packing on the device and the training driver: a gathered
+minibatch equals the one built from scratch, bit for bit (lists and results);
+training lowers the loss, switches stage at the configured epoch, and a run
+resumed from a checkpoint continues bit for bit like the uninterrupted run."""
+
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import device_inputs, fixture
+from synth import workload_batch
+
+pytestmark = pytest.mark.gpu
+
+N = pytest.importorskip("paper_2606_19557_amd")
+from paper_2606_19557_amd import train  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _dataset(name, idx, dtype="f32"):
+    md, m, b, th, s, tg = fixture(name, idx)
+    b, th, s, tg = device_inputs(dtype, b, th, s, tg)
+    model = N.Model.from_dict(md, dtype=dtype)
+    data = train.Dataset(model, b, *tg)
+    td = model.torch_dtype
+    return md, model, data, torch.tensor(th, dtype=td, device="cuda"), torch.tensor(s, dtype=td, device="cuda"), b, tg
+
+
+@pytest.mark.parametrize("name,dtype", [("fcc_uneven_256", "f32"), ("alloy4_1024", "f64")])
+def test_gather_equals_direct_build(name, dtype):
+    _say(f"gather {name} {dtype}")
+    idx = list(range(10))
+    md, model, data, theta, qs, b, tg = _dataset(name, idx, dtype)
+    pick = [7, 2, 9, 0, 4]
+    gb, gnb, gtg = data.minibatch(pick, lambdas=(1.0, 1.0, 0.1))
+    sub = b.subset(pick)
+    db = N.Batch.from_host(sub, dtype=model.torch_dtype)
+    dnb = N.nep_build_neighbors(model, db)
+    assert (gnb.num_pairs, gnb.num_angular_pairs) == (dnb.num_pairs, dnb.num_angular_pairs)
+    P = dnb.num_pairs
+    assert torch.equal(gb.atom_offset, db.atom_offset)
+    assert torch.equal(gb.positions, db.positions) and torch.equal(gb.types, db.types)
+    assert torch.equal(gb.cells, db.cells)
+    for k in ("row_offset", "seg_count", "atom_struct", "species_order", "species_offset"):
+        assert torch.equal(getattr(gnb, k), getattr(dnb, k)), k
+    assert torch.equal(gnb.pairs[:P], dnb.pairs[:P]) and torch.equal(gnb.reverse[:P], dnb.reverse[:P])
+    Et, Ft, Wt = tg
+    a0 = np.concatenate([np.arange(b.atom_offset[s], b.atom_offset[s + 1]) for s in pick])
+    dtg = N.Targets(Et[pick], Ft[a0], Wt[pick], lambdas=(1.0, 1.0, 0.1), dtype=model.torch_dtype)
+    assert torch.equal(gtg.energy, dtg.energy) and torch.equal(gtg.force, dtg.force)
+    assert torch.equal(gtg.virial, dtg.virial) and bool(torch.all(gtg.has_virial == 1))
+    l1, g1 = N.nep_loss_and_grad(model, theta, qs, gb, gnb, gtg)
+    l2, g2 = N.nep_loss_and_grad(model, theta, qs, db, dnb, dtg)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+
+
+def test_training_epochs_stage_switch_and_resume():
+    _say("train fcc 24 structures")
+    md, model, data, theta, qs, b, tg = _dataset("fcc_uneven_256", list(range(24)))
+    cfg = train.TrainConfig(epochs=4, batch_size=8, lr=2e-3, lambdas=(1.0, 1.0, 0.1), start_stage2=2,
+                            stage2_lr=1e-3, stage2_lambdas=(10.0, 1.0, 1.0), seed=3)
+    tr = train.Trainer(model, theta, qs, cfg, data)
+    first = tr.run_epoch(data)
+    second = tr.run_epoch(data)
+    assert tr.stage == 1 and tr.t == 6 and second[0] < first[0]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ckpt.pt")
+        tr.save(path)
+        third = tr.run_epoch(data)
+        assert tr.stage == 2 and tr.sched.lr == pytest.approx(1e-3)
+        fourth = tr.run_epoch(data)
+        tr2 = train.Trainer(model, theta, qs, cfg, data)
+        tr2.load(path)
+        assert tr2.epoch == 2 and tr2.t == 6
+        assert np.array_equal(tr2.run_epoch(data), third)
+        assert np.array_equal(tr2.run_epoch(data), fourth)
+        assert torch.equal(tr2.theta, tr.theta) and torch.equal(tr2.vmax, tr.vmax)
