@@ -106,7 +106,7 @@ const ShapeEntry* find_shape(const Dims& d) {
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 nep_status resolve_plan(const nep_plan* p, Plan* out) {
-    Plan q{kTeam, kTeam, kTeam, kTeam, kMaxAngRows, kOuterChunk};
+    Plan q{kTeam, kTeam, kTeam, kTeam, kMaxAngRows, kOuterChunk, kNetwork};
     if (p) {
         const int32_t teams[4] = {p->team_descriptor, p->team_force, p->team_tangent, p->team_coeff_grad};
         int* dst[4] = {&q.team_desc, &q.team_force, &q.team_tangent, &q.team_cg};
@@ -125,6 +125,11 @@ nep_status resolve_plan(const nep_plan* p, Plan* out) {
             if (p->outer_chunk < 8 || p->outer_chunk > 4096)
                 return fail(NEP_ERR_INVALID_ARG, "plan outer_chunk %d outside [8, 4096]", p->outer_chunk);
             q.outer_chunk = p->outer_chunk;
+        }
+        if (p->network != 0) {
+            if (p->network != 1 && p->network != 2)
+                return fail(NEP_ERR_INVALID_ARG, "plan network %d is not 1 or 2", p->network);
+            q.network = p->network;
         }
     }
     *out = q;
@@ -518,7 +523,7 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
         auto it = a.find(k);
         return it == a.end() ? 0.0 : it->second;
     };
-    nep_plan best{8, 8, 8, 8, kMaxAngRows, kOuterChunk};
+    nep_plan best{8, 8, 8, 8, kMaxAngRows, kOuterChunk, kNetwork};
     // phase 1: team sizes, all four sweeps at once; each kernel keeps its fastest
     {
         const int cand[3] = {4, 8, 16};
@@ -527,7 +532,7 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
                                    {"angular_coeff_grad", nullptr}};
         int32_t* field[4] = {&best.team_descriptor, &best.team_force, &best.team_tangent, &best.team_coeff_grad};
         for (int k = 0; k < 3; ++k) {
-            nep_plan p{cand[k], cand[k], cand[k], cand[k], kMaxAngRows, kOuterChunk};
+            nep_plan p{cand[k], cand[k], cand[k], cand[k], kMaxAngRows, kOuterChunk, kNetwork};
             std::map<std::string, double> avg;
             nep_status s = measure(p, &avg);
             if (skippable(s)) {
@@ -569,6 +574,28 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
             }
             const double t = get(avg, "angular_coeff_grad") + get(avg, "outer_grad") + get(avg, "reduce_stage") +
                              get(avg, "final_reduce");
+            if (t < tb) {
+                tb = t;
+                keep = p;
+            }
+        }
+        best = keep;
+    }
+    // phase 3: network implementation
+    {
+        double tb = 1e300;
+        nep_plan keep = best;
+        for (int k = 1; k <= 2; ++k) {
+            nep_plan p = best;
+            p.network = k;
+            std::map<std::string, double> avg;
+            nep_status s = measure(p, &avg);
+            if (skippable(s)) continue;
+            if (s) {
+                g_prof_on = was_on;
+                return s;
+            }
+            const double t = get(avg, "network_forward") + get(avg, "network_backward");
             if (t < tb) {
                 tb = t;
                 keep = p;

@@ -49,12 +49,14 @@ enum class Mode { Descriptors, Forward, LossGrad, Backward };
 struct Plan {
     int team_desc, team_force, team_tangent, team_cg;
     int cg_blocks, outer_chunk;
+    int network;  // 1 = matrix-core tiles, 2 = lane per atom
 };
 
 // Team size (lanes per atom) of the pair sweeps and the grid defaults.
 constexpr int kTeam = 8;
 constexpr int kMaxAngRows = 2048;
 constexpr int kOuterChunk = 64;
+constexpr int kNetwork = 1;
 
 // Defaults for zero fields; NEP_ERR_INVALID_ARG for values out of range.
 nep_status resolve_plan(const nep_plan* p, Plan* out);

@@ -791,8 +791,26 @@ struct OuterMma : Mfma<R> {
 //   W0[mu][nu] = sum_i alpha_mu (s q)_nu + beta_mu (s dq)_nu     (matrix cores),
 //   b0[mu] = -sum_i alpha_mu, w1[mu] = sum_i gamma_mu,
 //   c_R[a][b][n][k] = sum_i abar_n S0[b][k] + e_n S1[b][k]        (matrix cores).
-// Each wave accumulates its share of the chunk's atoms per output tile; the
-// four wave tiles are added in wave order through LDS.
+// The block walks its chunk in sub-chunks of SC atoms: every operand row of a
+// sub-chunk is copied once into LDS with coalesced loads (rows of the
+// per-unit arrays are contiguous in the species-sorted list), then each wave
+// updates the 32 x 32 (16 x 16 in FP64) output tiles it owns from LDS. A tile
+// belongs to one wave for the whole chunk, so its sums need no cross-wave step.
+template <typename R>
+struct OuterTiles {
+    static constexpr int SC = sizeof(R) == 4 ? 32 : 16;  // atoms per staged sub-chunk
+    static constexpr int MAXTW = 6;                        // tiles per wave
+    static constexpr int WAVES = kBlock / 64;
+    __host__ __device__ static int floats_per_atom(const Dims& d) {
+        return 3 * d.H + 2 * d.D + 2 * d.NR + 2 * d.T * d.KR;
+    }
+    __host__ __device__ static size_t lds_bytes(const Dims& d) { return sizeof(R) * size_t(SC) * floats_per_atom(d); }
+    __host__ __device__ static int tiles(const Dims& d) {
+        const int M = Mfma<R>::M;
+        return ((d.H + M - 1) / M) * ((d.D + M - 1) / M) + ((d.NR + M - 1) / M) * ((d.T * d.KR + M - 1) / M);
+    }
+};
+
 template <typename R, class Sh>
 __global__ void __launch_bounds__(kBlock)
 k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict__ order,
@@ -801,9 +819,10 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
              const R* __restrict__ beta, const R* __restrict__ gam, const R* __restrict__ S0,
              const R* __restrict__ S1, double* __restrict__ partial) {
     using MM = OuterMma<R>;
-    constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D;
-    constexpr int WAVES = kBlock / 64;
-    __shared__ R tile_buf[WAVES][M * M];
+    using OT = OuterTiles<R>;
+    constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D, SC = OT::SC, MAXTW = OT::MAXTW;
+    constexpr int WAVES = OT::WAVES, KSTEPS = 2 * SC / MM::KPI;
+    extern __shared__ __align__(16) unsigned char outer_smem[];
     const int T = dm.T, H = dm.H, TK = T * KR;
     const int W1 = (D + 2) * H + T * NR * KR;
     double* __restrict__ rowp = partial + (long)blockIdx.x * (W1 + 1);
@@ -812,100 +831,108 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
     species_chunk(soff, T, chunk, blockIdx.x, &a, &lo, &hi);
     if (threadIdx.x == 0) rowp[0] = double(a);
     if (a < 0) return;
+    // LDS sub-chunk: alpha, beta, gamma [SC][H]; s q, s dq [SC][D]; abar, e [SC][NR]; S0, S1 [SC][TK]
+    R* Xa = reinterpret_cast<R*>(outer_smem);
+    R* Xb = Xa + SC * H;
+    R* Xg = Xb + SC * H;
+    R* Yq = Xg + SC * H;
+    R* Yd = Yq + SC * D;
+    R* Ra = Yd + SC * D;
+    R* Re = Ra + SC * NR;
+    R* C0 = Re + SC * NR;
+    R* C1 = C0 + SC * TK;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int srow = lane % M, satom = MM::slot_atom(lane), sterm = MM::slot_term(lane);
-    // this wave's atoms: sorted positions lo + wave, lo + wave + WAVES, ...
-    const int tilesH = (H + M - 1) / M, tilesD = (D + M - 1) / M;
-    const int tilesR = (NR + M - 1) / M, tilesC = (TK + M - 1) / M;
-    const int ntiles = tilesH * tilesD + tilesR * tilesC;
-    for (int tl = 0; tl < ntiles; ++tl) {
-        const bool wtile = tl < tilesH * tilesD;
-        const int r0 = (wtile ? tl / tilesD : (tl - tilesH * tilesD) / tilesC) * M;
-        const int c0 = (wtile ? tl % tilesD : (tl - tilesH * tilesD) % tilesC) * M;
-        const int rr = r0 + srow, cc = c0 + srow;
-        typename MM::Acc acc;
+    const int tilesD = (D + M - 1) / M, tilesC = (TK + M - 1) / M;
+    const int nW = ((H + M - 1) / M) * tilesD, ntiles = nW + ((NR + M - 1) / M) * tilesC;
+    typename MM::Acc acc[MAXTW];
 #pragma unroll
-        for (int v = 0; v < MM::NV; ++v) acc[v] = R(0);
-        const R sc = (wtile && cc < D) ? qscale[cc] : R(1);
-        // batches of U instructions: all operand loads first, then the MFMAs
-        constexpr int U = 8;
-        const long stride = long(WAVES) * MM::ATOMS;
-        for (long s0 = lo + long(wave) * MM::ATOMS; s0 < hi; s0 += stride * U) {
-            R xs[U], ys[U];
+    for (int k = 0; k < MAXTW; ++k)
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const long sa = s0 + u * stride + satom;
-                xs[u] = ys[u] = R(0);
-                if (sa < hi) {
-                    const long i = order[sa];
-                    if (wtile) {
-                        if (rr < H) xs[u] = (sterm ? beta : alpha)[sa * H + rr];
-                        if (cc < D) ys[u] = sc * (sterm ? dq_in : q_in)[i * D + cc];
-                    } else {
-                        if (rr < NR) xs[u] = (sterm ? e_in : abar)[i * D + rr];
-                        if (cc < TK) ys[u] = (sterm ? S1 : S0)[i * TK + cc];
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc = MM::mma(xs[u], ys[u], acc);
+        for (int v = 0; v < MM::NV; ++v) acc[k][v] = R(0);
+    R sa = R(0), sg = R(0);  // b0 / w1 column sums of unit mu = threadIdx.x (H <= kBlock)
+    for (long s0 = lo; s0 < hi; s0 += SC) {
+        const int n = int(hi - s0 < SC ? hi - s0 : SC);
+        __syncthreads();
+        // per-unit rows: contiguous in the species-sorted list
+        for (int x = threadIdx.x; x < SC * H; x += kBlock) {
+            const bool in = x < n * H;
+            Xa[x] = in ? alpha[s0 * H + x] : R(0);
+            Xb[x] = in ? beta[s0 * H + x] : R(0);
+            Xg[x] = in ? gam[s0 * H + x] : R(0);
+        }
+        // per-atom rows, gathered by atom index
+        for (int x = threadIdx.x; x < SC * D; x += kBlock) {
+            const int sl = x / D, v = x % D;
+            const bool in = sl < n;
+            const long i = in ? long(order[s0 + sl]) : 0;
+            Yq[x] = in ? qscale[v] * q_in[i * D + v] : R(0);
+            Yd[x] = in ? qscale[v] * dq_in[i * D + v] : R(0);
+        }
+        for (int x = threadIdx.x; x < SC * NR; x += kBlock) {
+            const int sl = x / NR, r = x % NR;
+            const bool in = sl < n;
+            const long i = in ? long(order[s0 + sl]) : 0;
+            Ra[x] = in ? abar[i * D + r] : R(0);
+            Re[x] = in ? e_in[i * D + r] : R(0);
+        }
+        for (int x = threadIdx.x; x < SC * TK; x += kBlock) {
+            const int sl = x / TK, c = x % TK;
+            const bool in = sl < n;
+            const long i = in ? long(order[s0 + sl]) : 0;
+            C0[x] = in ? S0[i * TK + c] : R(0);
+            C1[x] = in ? S1[i * TK + c] : R(0);
         }
         __syncthreads();
+        if (threadIdx.x < H)
+            for (int sl = 0; sl < n; ++sl) {
+                sa += Xa[sl * H + threadIdx.x];
+                sg += Xg[sl * H + threadIdx.x];
+            }
 #pragma unroll
-        for (int v = 0; v < MM::NV; ++v) tile_buf[wave][MM::c_row(lane, v) * M + (lane % M)] = acc[v];
-        __syncthreads();
-        for (int x = threadIdx.x; x < M * M; x += kBlock) {
-            R sum = R(0);
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) sum += tile_buf[w][x];
-            const int r = r0 + x / M, c = c0 + x % M;
-            if (wtile) {
-                if (r < H && c < D) rowp[1 + r * D + c] = double(sum);
-            } else if (r < NR && c < TK) {
-                const int b = c / KR, k = c % KR;
-                rowp[1 + (D + 2) * H + (b * NR + r) * KR + k] = double(sum);
+        for (int k = 0; k < MAXTW; ++k) {
+            const int tl = wave + WAVES * k;
+            if (tl >= ntiles) continue;
+            const bool wtile = tl < nW;
+            const int r0 = (wtile ? tl / tilesD : (tl - nW) / tilesC) * M;
+            const int c0 = (wtile ? tl % tilesD : (tl - nW) % tilesC) * M;
+            const int rr = r0 + srow, cc = c0 + srow;
+            const int RN = wtile ? H : NR, CN = wtile ? D : TK;
+            const R* Xs = wtile ? (sterm ? Xb : Xa) : (sterm ? Re : Ra);
+            const R* Ys = wtile ? (sterm ? Yd : Yq) : (sterm ? C1 : C0);
+#pragma unroll 4
+            for (int kb = 0; kb < KSTEPS; ++kb) {
+                const int sl = kb * MM::ATOMS + satom;
+                const R xv = rr < RN ? Xs[sl * RN + rr] : R(0);
+                const R yv = cc < CN ? Ys[sl * CN + cc] : R(0);
+                acc[k] = MM::mma(xv, yv, acc[k]);
             }
         }
     }
-    // b0 and w1 columns: sums over the chunk, lanes over neurons, waves over
-    // atoms, wave sums added in wave order
-    R* red = &tile_buf[0][0];
-    for (int mu0 = 0; mu0 < H; mu0 += 64) {
-        const int mu = mu0 + lane;
-        R sa = R(0), sg = R(0);
-        if (mu < H)
-            for (long s0 = lo + wave; s0 < hi; s0 += 8 * WAVES) {
-                R xa[8], xg[8];
+    // each wave writes the tiles it owns
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const long sidx = s0 + u * WAVES;
-                    xa[u] = xg[u] = R(0);
-                    if (sidx < hi) {
-                        xa[u] = alpha[sidx * H + mu];
-                        xg[u] = gam[sidx * H + mu];
-                    }
-                }
+    for (int k = 0; k < MAXTW; ++k) {
+        const int tl = wave + WAVES * k;
+        if (tl >= ntiles) continue;
+        const bool wtile = tl < nW;
+        const int r0 = (wtile ? tl / tilesD : (tl - nW) / tilesC) * M;
+        const int c0 = (wtile ? tl % tilesD : (tl - nW) % tilesC) * M;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    sa += xa[u];
-                    sg += xg[u];
-                }
+        for (int v = 0; v < MM::NV; ++v) {
+            const int r = r0 + MM::c_row(lane, v), c = c0 + lane % M;
+            if (wtile) {
+                if (r < H && c < D) rowp[1 + r * D + c] = double(acc[k][v]);
+            } else if (r < NR && c < TK) {
+                const int b = c / KR, kk = c % KR;
+                rowp[1 + (D + 2) * H + (b * NR + r) * KR + kk] = double(acc[k][v]);
             }
-        __syncthreads();
-        red[wave * 64 + lane] = sa;
-        red[(WAVES + wave) * 64 + lane] = sg;
-        __syncthreads();
-        if (wave == 0 && mu < H) {
-            R ta = R(0), tg = R(0);
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                ta += red[w * 64 + lane];
-                tg += red[(WAVES + w) * 64 + lane];
-            }
-            rowp[1 + H * D + mu] = -double(ta);
-            rowp[1 + H * D + H + mu] = double(tg);
         }
-    }}
+    }
+    if (threadIdx.x < H) {
+        rowp[1 + H * D + threadIdx.x] = -double(sa);
+        rowp[1 + H * D + H + threadIdx.x] = double(sg);
+    }
+}
 
 // ------------------------------------------------- network on matrix cores
 
@@ -1110,6 +1137,136 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
             const int nu = dt * M + MM::c_row(lane, v);
             if (nu < D && ia >= 0) abar_out[ia * D + nu] = eb * e_in[ia * D + nu] + qscale[nu] * zacc[dt][v];
         }
+}
+
+// ------------------------------------------------- network, one lane per atom
+
+// The same network passes with one lane per atom: a block is one wavefront of
+// up to 64 atoms of one species (species-sorted list), so every lane reads the
+// same weight row at the same time (wave-uniform addresses, scalar loads) and
+// the loop over hidden units needs no exchange between lanes. Per-unit values
+// go through an LDS tile [atom][unit] to whole-line stores.
+template <typename R>
+struct LaneNet {
+    static constexpr int MC = sizeof(R) == 4 ? 32 : 16;  // hidden units per LDS tile
+};
+
+template <typename R, class Sh>
+__global__ void __launch_bounds__(64)
+k_network_forward_lane(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
+                       const int* __restrict__ order, const int64_t* __restrict__ soff, const R* __restrict__ q_in,
+                       R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out) {
+    constexpr int D = Sh::D, MC = LaneNet<R>::MC;
+    __shared__ R tb[64 * (MC + 1)];
+    const int T = dm.T, H = dm.H;
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, 64, blockIdx.x, &a, &lo, &hi);
+    if (a < 0) return;
+    const int l = threadIdx.x;
+    const int nat = int(hi - lo);
+    const bool live = l < nat;
+    const long ia = order[live ? lo + l : lo];
+    const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
+    const R* __restrict__ b0 = W0 + (long)H * D;
+    const R* __restrict__ w1 = b0 + H;
+    R qv[D], ev[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        qv[v] = qscale[v] * q_in[ia * D + v];
+        ev[v] = R(0);
+    }
+    R E = R(0);
+    for (int mu0 = 0; mu0 < H; mu0 += MC) {
+        const int mn = H - mu0 < MC ? H - mu0 : MC;
+        for (int m = 0; m < mn; ++m) {
+            const R* __restrict__ w = W0 + (long)(mu0 + m) * D;
+            R acc = -b0[mu0 + m];
+#pragma unroll
+            for (int v = 0; v < D; ++v) acc += w[v] * qv[v];
+            const R t = tanh_<R>(acc);
+            const R wm = w1[mu0 + m];
+            E += wm * t;
+            const R c = wm * (R(1) - t * t);
+#pragma unroll
+            for (int v = 0; v < D; ++v) ev[v] += w[v] * c;
+            tb[l * (MC + 1) + m] = t;
+        }
+        __syncthreads();
+        for (int x = l; x < nat * mn; x += 64) {
+            const int sl = x / mn, m = x % mn;
+            t_out[(lo + sl) * H + mu0 + m] = tb[sl * (MC + 1) + m];
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    E_out[ia] = E - theta[dm.offB1];
+#pragma unroll
+    for (int v = 0; v < D; ++v) e_out[ia * D + v] = qscale[v] * ev[v];
+}
+
+template <typename R, class Sh>
+__global__ void __launch_bounds__(64)
+k_network_backward_lane(const Dims dm, const R* __restrict__ theta, const R* __restrict__ qscale,
+                        const int* __restrict__ order, const int64_t* __restrict__ soff,
+                        const int* __restrict__ atom_struct, const double* __restrict__ ebar_s,
+                        const R* __restrict__ dq_in, const R* __restrict__ e_in, const R* __restrict__ t_in,
+                        R* __restrict__ abar_out, R* __restrict__ alpha_out, R* __restrict__ beta_out,
+                        R* __restrict__ gamma_out) {
+    constexpr int D = Sh::D, MC = LaneNet<R>::MC, LD = MC + 1;
+    __shared__ R tb[4][64 * LD];
+    const int T = dm.T, H = dm.H;
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, 64, blockIdx.x, &a, &lo, &hi);
+    if (a < 0) return;
+    const int l = threadIdx.x;
+    const int nat = int(hi - lo);
+    const bool live = l < nat;
+    const long ia = order[live ? lo + l : lo];
+    const R eb = live ? R(ebar_s[atom_struct[ia]]) : R(0);
+    const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
+    const R* __restrict__ w1 = W0 + (long)H * D + H;
+    R dk[D], z[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        dk[v] = qscale[v] * dq_in[ia * D + v];
+        z[v] = R(0);
+    }
+    for (int mu0 = 0; mu0 < H; mu0 += MC) {
+        const int mn = H - mu0 < MC ? H - mu0 : MC;
+        for (int x = l; x < nat * mn; x += 64) {
+            const int sl = x / mn, m = x % mn;
+            tb[3][sl * LD + m] = t_in[(lo + sl) * H + mu0 + m];
+        }
+        __syncthreads();
+        for (int m = 0; m < mn; ++m) {
+            const R* __restrict__ w = W0 + (long)(mu0 + m) * D;
+            R da = R(0);
+#pragma unroll
+            for (int v = 0; v < D; ++v) da += w[v] * dk[v];
+            const R t = live ? tb[3][l * LD + m] : R(0);
+            const R sp = R(1) - t * t, wm = w1[mu0 + m];
+            tb[0][l * LD + m] = wm * sp * (eb - R(2) * t * da);
+            tb[1][l * LD + m] = wm * sp;
+            tb[2][l * LD + m] = eb * t + sp * da;
+            const R c2 = R(-2) * wm * t * sp * da;
+#pragma unroll
+            for (int v = 0; v < D; ++v) z[v] += w[v] * c2;
+        }
+        __syncthreads();
+        for (int x = l; x < nat * mn; x += 64) {
+            const int sl = x / mn, m = x % mn;
+            const long o = (lo + sl) * H + mu0 + m;
+            alpha_out[o] = tb[0][sl * LD + m];
+            beta_out[o] = tb[1][sl * LD + m];
+            gamma_out[o] = tb[2][sl * LD + m];
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+#pragma unroll
+    for (int v = 0; v < D; ++v) abar_out[ia * D + v] = eb * e_in[ia * D + v] + qscale[v] * z[v];
 }
 
 }  // namespace nep

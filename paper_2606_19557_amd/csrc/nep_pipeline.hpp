@@ -32,10 +32,14 @@ nep_status run_shape(const Ctx& c) {
     const size_t cg_shm = with_team_size<size_t>(c.plan.team_cg, [&](auto S_) {
         return CoeffGradSmem<R, Sh, decltype(S_)::value>::bytes(dm.T);
     });
-    if (c.mode == Mode::LossGrad || c.mode == Mode::Backward)
+    if (c.mode == Mode::LossGrad || c.mode == Mode::Backward) {
         if (cg_shm > 160 * 1024)
             return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block of %d-lane teams needs %zu bytes of LDS",
                         c.plan.team_cg, cg_shm);
+        if (OuterTiles<R>::lds_bytes(dm) > 160 * 1024 || dm.H > kBlock ||
+            OuterTiles<R>::tiles(dm) > OuterTiles<R>::WAVES * OuterTiles<R>::MAXTW)
+            return fail(NEP_ERR_UNSUPPORTED, "network of %d hidden units too large for the outer-product tiles", dm.H);
+    }
 
     R* q = (c.mode == Mode::Descriptors || c.desc_out) && c.desc_out ? static_cast<R*>(c.desc_out) : Wr(L.q);
     if (Na > 0 && (rs = with_team(c.plan.team_desc, [&](auto S_) -> nep_status {
@@ -47,8 +51,12 @@ nep_status run_shape(const Ctx& c) {
         return rs;
     if (c.mode == Mode::Descriptors) return NEP_OK;
 
-    const int net_grid = int((c.Na + Mfma<R>::M - 1) / Mfma<R>::M) + dm.T;
-    if (Na > 0)
+    const bool lane_net = c.plan.network == 2;
+    const int net_grid = lane_net ? int((c.Na + 63) / 64) + dm.T : int((c.Na + Mfma<R>::M - 1) / Mfma<R>::M) + dm.T;
+    if (Na > 0 && lane_net)
+        NEP_LAUNCH("network_forward", (k_network_forward_lane<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
+                   qscale, c.species_order, c.species_offset, q, Wr(L.Eat), Wr(L.e), Wr(L.t));
+    if (Na > 0 && !lane_net)
         NEP_LAUNCH("network_forward", (k_network_forward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta, qscale,
                    c.species_order, c.species_offset, q, Wr(L.Eat), Wr(L.e), Wr(L.t));
 
@@ -89,9 +97,14 @@ nep_status run_shape(const Ctx& c) {
                 return NEP_OK;
             })))
             return rs;
-        NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
-                   qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e), Wr(L.t),
-                   Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
+        if (lane_net)
+            NEP_LAUNCH("network_backward", (k_network_backward_lane<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm,
+                       theta, qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq),
+                       Wr(L.e), Wr(L.t), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
+        else
+            NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
+                       qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e),
+                       Wr(L.t), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
         if ((rs = with_team(c.plan.team_cg, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
                 if (cg_shm > 64 * 1024)
@@ -103,7 +116,11 @@ nep_status run_shape(const Ctx& c) {
                 return NEP_OK;
             })))
             return rs;
-        NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), 0, st, dm, qscale,
+        const size_t og_shm = OuterTiles<R>::lds_bytes(dm);
+        if (og_shm > 64 * 1024)
+            NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_outer_grad<R, Sh>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(og_shm)));
+        NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), og_shm, st, dm, qscale,
                    c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha),
                    Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));
     }

@@ -33,7 +33,8 @@ class NepError(RuntimeError):
 
 class c_plan(C.Structure):
     _fields_ = [("team_descriptor", C.c_int32), ("team_force", C.c_int32), ("team_tangent", C.c_int32),
-                ("team_coeff_grad", C.c_int32), ("coeff_grad_blocks", C.c_int32), ("outer_chunk", C.c_int32)]
+                ("team_coeff_grad", C.c_int32), ("coeff_grad_blocks", C.c_int32), ("outer_chunk", C.c_int32),
+                ("network", C.c_int32)]
 
 
 class c_model(C.Structure):
@@ -129,10 +130,11 @@ class Plan:
     team_coeff_grad: int = 0
     coeff_grad_blocks: int = 0
     outer_chunk: int = 0
+    network: int = 0  # 1 = matrix-core tiles, 2 = one lane per atom
 
     def c(self) -> c_plan:
         return c_plan(self.team_descriptor, self.team_force, self.team_tangent, self.team_coeff_grad,
-                      self.coeff_grad_blocks, self.outer_chunk)
+                      self.coeff_grad_blocks, self.outer_chunk, self.network)
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k in self.__dataclass_fields__}
@@ -425,7 +427,7 @@ def nep_autotune(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, tar
     _check(lib().nep_autotune(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), C.byref(tg),
                               _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), int(repeats), C.byref(out), _stream()))
     return Plan(out.team_descriptor, out.team_force, out.team_tangent, out.team_coeff_grad, out.coeff_grad_blocks,
-                out.outer_chunk)
+                out.outer_chunk, out.network)
 
 
 @dataclass

@@ -108,7 +108,7 @@ def test_plan_validation_and_workspace():
     big = nep.nep_workspace_size(m.with_plan(nep.Plan(outer_chunk=8)), 10, 5000, 200000)
     assert small < base < big
     for bad in (nep.Plan(team_descriptor=5), nep.Plan(team_force=32), nep.Plan(coeff_grad_blocks=-1),
-                nep.Plan(outer_chunk=4), nep.Plan(outer_chunk=5000)):
+                nep.Plan(outer_chunk=4), nep.Plan(outer_chunk=5000), nep.Plan(network=3)):
         with pytest.raises(nep.NepError) as e:
             nep.nep_workspace_size(m.with_plan(bad), 10, 5000, 200000)
         assert e.value.code == nep.NEP_ERR_INVALID_ARG

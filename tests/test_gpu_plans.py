@@ -14,10 +14,10 @@ pytestmark = pytest.mark.gpu
 N = pytest.importorskip("paper_2606_19557_amd")
 
 PLANS = [
-    N.Plan(4, 4, 4, 4, 512, 32),
-    N.Plan(16, 16, 16, 16, 4096, 256),
-    N.Plan(4, 16, 8, 16, 1, 8),
-    N.Plan(16, 4, 16, 8, 7, 100),
+    N.Plan(4, 4, 4, 4, 512, 32, 1),
+    N.Plan(16, 16, 16, 16, 4096, 256, 2),
+    N.Plan(4, 16, 8, 16, 1, 8, 1),
+    N.Plan(16, 4, 16, 8, 7, 100, 2),
 ]
 
 
@@ -68,6 +68,7 @@ def test_autotune_returns_valid_plan():
     for k in ("team_descriptor", "team_force", "team_tangent", "team_coeff_grad"):
         assert getattr(plan, k) in (4, 8, 16)
     assert plan.coeff_grad_blocks in (512, 1024, 2048, 4096) and plan.outer_chunk in (32, 64, 128, 256)
+    assert plan.network in (1, 2)
     tuned = model.with_plan(plan)
     l0, g0 = N.nep_loss_and_grad(model, theta, qs, gb, nb, targets)
     l1, g1 = N.nep_loss_and_grad(tuned, theta, qs, gb, nb, targets)
