@@ -46,6 +46,7 @@ def parse():
     p.add_argument("--no-comparator", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-autotune", action="store_true", help="use the default launch plan")
+    p.add_argument("--retune", action="store_true", help="tune the launch plan even when one is cached")
     p.add_argument("--cpu-structures", type=int, default=256)
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="repeat the oracle over the sample until this much time has passed")
@@ -221,12 +222,17 @@ def main():
             f"{sizes[:, 1].mean():.0f} pairs")
     else:
         tune_b, tune_nb, tune_tg = gb, nb, targets
-    plan = None
+    plan, plan_cached = None, False
     if not args.no_autotune:
+        from paper_2606_19557_amd import tuning
+
         t0 = time.perf_counter()
-        plan = N.nep_autotune(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3)
+        if args.retune:
+            plan = N.nep_autotune(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3)
+        else:
+            plan, plan_cached = tuning.tuned_plan(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3)
         model = model.with_plan(plan)
-        log(f"autotuned plan in {time.perf_counter() - t0:.2f} s: {plan.as_dict()}")
+        log(f"{'cached' if plan_cached else 'autotuned'} plan in {time.perf_counter() - t0:.2f} s: {plan.as_dict()}")
     if epoch_mode:
         data.model = model
         big = int(np.argmax(sizes[:, 1]))
@@ -398,7 +404,7 @@ def main():
         "config": {"workload": f"{args.workload}: {w.description}",
                    "structures": host.num_structures, "atoms": host.num_atoms, "pairs": nb.num_pairs,
                    "angular_pairs": nb.num_angular_pairs, "parallelism": "single GPU",
-                   "plan": None if plan is None else plan.as_dict(),
+                   "plan": None if plan is None else dict(plan.as_dict(), from_cache=plan_cached),
                    **({"minibatch": w.minibatch, "steps_per_epoch": len(mbs),
                        "epoch_s": round(ms * len(mbs) * 1e-3, 5)} if epoch_mode else {})},
         "roofline": roof,

@@ -57,3 +57,30 @@ def test_defaults_are_table1():
     assert c.lambdas == (s1["lambda_e"], s1["lambda_f"], s1["lambda_v"])
     assert (c.start_stage2, c.stage2_lr) == (s2["start_stage2"], s2["stage2_lr"])
     assert c.stage2_lambdas == (s2["stage2_lambda_e"], s2["stage2_lambda_f"], s2["stage2_lambda_v"])
+
+
+def test_plan_cache_roundtrip(tmp_path):
+    """The tuned-plan cache: a miss tunes and stores, a hit for the same kind of
+    batch returns the stored plan without tuning; a different density misses."""
+    from types import SimpleNamespace
+
+    from paper_2606_19557_amd import nep, tuning
+
+    calls = []
+
+    def fake_tuner(model, theta, qs, batch, nbr, targets, repeats=3):
+        calls.append(repeats)
+        return nep.Plan(4, 8, 16, 8, 1024, 128, 2)
+
+    m = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30)
+    path = str(tmp_path / "plans.json")
+    b1, n1 = SimpleNamespace(num_atoms=36391), SimpleNamespace(num_pairs=1757148)
+    p, cached = tuning.tuned_plan(m, None, None, b1, n1, None, path=path, tuner=fake_tuner)
+    assert not cached and p == nep.Plan(4, 8, 16, 8, 1024, 128, 2) and calls == [3]
+    b2, n2 = SimpleNamespace(num_atoms=40000), SimpleNamespace(num_pairs=1900000)  # same buckets
+    p2, cached2 = tuning.tuned_plan(m, None, None, b2, n2, None, path=path, tuner=fake_tuner)
+    assert cached2 and p2 == p and calls == [3]
+    b3, n3 = SimpleNamespace(num_atoms=36391), SimpleNamespace(num_pairs=36391 * 100)  # denser
+    _, cached3 = tuning.tuned_plan(m, None, None, b3, n3, None, path=path, tuner=fake_tuner)
+    assert not cached3 and len(calls) == 2
+    assert len(tuning.load(path)) == 2
