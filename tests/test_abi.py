@@ -112,3 +112,32 @@ def test_plan_validation_and_workspace():
         with pytest.raises(nep.NepError) as e:
             nep.nep_workspace_size(m.with_plan(bad), 10, 5000, 200000)
         assert e.value.code == nep.NEP_ERR_INVALID_ARG
+
+
+def test_gather_and_autotune_validate_before_launching():
+    """The minibatch gather and the autotuner reject NULL or negative arguments on the host."""
+    L = _lib_or_skip()
+    m = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30).c()
+    batch = nep.c_batch(1, 4, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8))
+    nb = nep.c_neighbors(16, *([C.c_void_p(8)] * 7), 8, 4)
+    dst = nep.c_neighbors(16, *([C.c_void_p(8)] * 7), 0, 0)
+    vp = C.c_void_p(8)
+    # NULL ids with structures selected
+    rc = L.nep_gather_batch(C.byref(m), C.byref(batch), C.byref(nb), None, None, 2, 4, vp, vp, vp, vp,
+                            C.byref(dst), None, None, None, None, vp, 64, None)
+    assert rc == nep.NEP_ERR_INVALID_ARG and L.nep_last_error()
+    # negative sizes
+    rc = L.nep_gather_batch(C.byref(m), C.byref(batch), C.byref(nb), None, vp, -1, 4, vp, vp, vp, vp,
+                            C.byref(dst), None, None, None, None, vp, 64, None)
+    assert rc == nep.NEP_ERR_INVALID_ARG
+    # no workspace
+    rc = L.nep_gather_batch(C.byref(m), C.byref(batch), C.byref(nb), None, vp, 2, 4, vp, vp, vp, vp,
+                            C.byref(dst), None, None, None, None, None, 0, None)
+    assert rc == nep.NEP_ERR_INVALID_ARG
+    # autotune: repeats out of range, missing output
+    out = nep.c_plan()
+    rc = L.nep_autotune(C.byref(m), vp, vp, C.byref(batch), C.byref(nb), None, vp, vp, vp, 1 << 20, 0,
+                        C.byref(out), None)
+    assert rc == nep.NEP_ERR_INVALID_ARG
+    rc = L.nep_autotune(C.byref(m), vp, vp, C.byref(batch), C.byref(nb), None, vp, vp, vp, 1 << 20, 3, None, None)
+    assert rc == nep.NEP_ERR_INVALID_ARG

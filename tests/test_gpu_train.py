@@ -81,3 +81,22 @@ def test_training_epochs_stage_switch_and_resume():
         assert np.array_equal(tr2.run_epoch(data), third)
         assert np.array_equal(tr2.run_epoch(data), fourth)
         assert torch.equal(tr2.theta, tr.theta) and torch.equal(tr2.vmax, tr.vmax)
+
+
+def test_gather_out_of_range_ids_are_empty_structures():
+    """An id outside [0, Ns) selects an empty structure (no atoms, zero targets,
+    virial mask 0) and the other structures are packed as usual."""
+    _say("gather out-of-range ids")
+    md, model, data, theta, qs, b, tg = _dataset("fcc_uneven_256", [0, 1, 2])
+    na, npairs, nang = data.sizes([2, 0])
+    ids = torch.tensor([2, -5, 0, 99], dtype=torch.int32, device="cuda")
+    gb, gnb, gtg = N.nep_gather_batch(model, data.batch, data.nbr, data.targets, ids, na, npairs, nang)
+    off = gb.atom_offset.cpu().numpy()
+    assert list(np.diff(off)) == [data.atoms[2], 0, data.atoms[0], 0]
+    assert gtg.has_virial.cpu().tolist() == [1, 0, 1, 0]
+    assert float(gtg.energy[1]) == 0.0 and float(gtg.energy[3]) == 0.0
+    direct = N.Batch.from_host(b.subset([2, 0]), dtype=model.torch_dtype)
+    dnb = N.nep_build_neighbors(model, direct)
+    P = dnb.num_pairs
+    assert torch.equal(gnb.pairs[:P], dnb.pairs[:P]) and torch.equal(gnb.reverse[:P], dnb.reverse[:P])
+    assert torch.equal(gb.positions, direct.positions)
