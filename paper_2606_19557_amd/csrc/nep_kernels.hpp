@@ -384,6 +384,16 @@ k_force_gather(int Na, const int64_t* __restrict__ row, const int* __restrict__ 
     if (live && lane < 3) F_out[(long)i * 3 + lane] = Fown[(long)i * 3 + lane] + (lane == 0 ? f[0] : (lane == 1 ? f[1] : f[2]));
 }
 
+// Occupancy request of the tangent sweep (waves per SIMD its registers must
+// allow). For small moment blocks (N_A x 24 <= 120) with teams of 8 the
+// compiler fits 3 waves with 28 bytes per lane spilled, which measures faster
+// than 2 waves without; other team sizes and larger shapes would spill
+// hundreds of bytes per lane, so they keep the unconstrained allocation.
+template <class Sh, int S>
+struct SweepWaves {
+    static constexpr int tangent = (Sh::NA * Sh::LM <= 120 && S == 8) ? 3 : 1;
+};
+
 // ----------------------------------------------------------------- tangent
 
 // Directional derivative of the descriptor along v_ij = u_i - u_j - U_s^T r_ij:
@@ -391,7 +401,7 @@ k_force_gather(int Na, const int64_t* __restrict__ row, const int* __restrict__ 
 // and S1[b][k] = sum_{j in b} (v.r^) f_k'. Angular pairs go through the team
 // exchange (two terms per pair); each lane owns the moments lm = lane + S*o.
 template <typename R, class Sh, int S>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (SweepWaves<Sh, S>::tangent))
 k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types,
           const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row, const int* __restrict__ seg,
           const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar, const double* __restrict__ Ubar,
