@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--no-autotune", action="store_true", help="use the default launch plan")
     p.add_argument("--retune", action="store_true", help="tune the launch plan even when one is cached")
     p.add_argument("--cpu-structures", type=int, default=256)
+    p.add_argument("--cpu-threads", type=int, default=0,
+                   help="oracle threads for the CPU baseline (default: the host's cores, at most 16)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="repeat the oracle over the sample until this much time has passed")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -69,7 +71,7 @@ def parse():
 
 Y_VAL = 82      # the 24 real solid harmonics of a unit vector
 Y_DIR = 214     # harmonics and their derivative along one vector (dual numbers)
-Y_GRAD = 478    # harmonics and their full gradient (dual numbers)
+Y_CGRAD = 241   # gradient of one linear combination of the 24 harmonics (closed form)
 PAIR_GEOM = 9   # |r| (3 FMA + sqrt), 1/r, unit vector
 
 
@@ -103,7 +105,7 @@ def work_model(name, md, n):
                 na * (4 + r * (D + 1 + D + H)))
     if name == "force":
         pair_r = PAIR_GEOM + basis_flops(KR, True) + 2 * KR + 3 + 6 + 18
-        pair_a = basis_flops(KA, True) + Y_GRAD + 4 * NA * KA + 4 * NA * LM + 11 * LM + 12
+        pair_a = basis_flops(KA, True) + Y_VAL + Y_CGRAD + 4 * NA * KA + 4 * NA * LM + 2 * LM + 5 + 12
         atom = B_atom + T * 2 * NR * KR
         return (npr * pair_r + nang * pair_a + na * atom,
                 rec + 4 * npr + idx + na * r * (NA * LM + D + 3 + 9) + rec)
@@ -368,7 +370,7 @@ def main():
         n_s = min(args.cpu_structures, host.num_structures)
         sub = host.subset(range(n_s))
         om = O.Model(**w.model)
-        cores = min(os.cpu_count() or 1, 16)
+        cores = args.cpu_threads if args.cpu_threads > 0 else min(os.cpu_count() or 1, 16)
         th_h = th.double().cpu().numpy()
         qs_h = qs.double().cpu().numpy()
         a0 = int(sub.atom_offset[-1])

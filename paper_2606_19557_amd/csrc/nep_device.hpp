@@ -124,22 +124,6 @@ __device__ __forceinline__ D1<R> operator*(D1<R> a, D1<R> b) { return {a.v * b.v
 template <typename R>
 __device__ __forceinline__ D1<R> operator*(R s, D1<R> a) { return {s * a.v, s * a.d}; }
 
-// Value and full gradient.
-template <typename R>
-struct G3 {
-    R v, x, y, z;
-};
-template <typename R>
-__device__ __forceinline__ G3<R> operator+(G3<R> a, G3<R> b) { return {a.v + b.v, a.x + b.x, a.y + b.y, a.z + b.z}; }
-template <typename R>
-__device__ __forceinline__ G3<R> operator-(G3<R> a, G3<R> b) { return {a.v - b.v, a.x - b.x, a.y - b.y, a.z - b.z}; }
-template <typename R>
-__device__ __forceinline__ G3<R> operator*(G3<R> a, G3<R> b) {
-    return {a.v * b.v, a.v * b.x + a.x * b.v, a.v * b.y + a.y * b.v, a.v * b.z + a.z * b.v};
-}
-template <typename R>
-__device__ __forceinline__ G3<R> operator*(R s, G3<R> a) { return {s * a.v, s * a.x, s * a.y, s * a.z}; }
-
 // Real orthonormal solid harmonics R_lm(x, y, z), homogeneous of degree l,
 // equal to Y_lm on the unit sphere; order l = 1..L, m = -l..l.
 // N is any number type with +, -, * and scalar multiplication.
@@ -185,6 +169,60 @@ __device__ __forceinline__ void solid_harmonics(const N& x, const N& y, const N&
     Y[21] = R(C42B) * (x2my2 * t42);
     Y[22] = R(C43) * (xz * (x2 - R(3) * y2));
     Y[23] = R(C44B) * (x2 * (x2 - R(3) * y2) - y2 * (R(3) * x2 - y2));
+}
+
+// g = grad_(x,y,z) sum_lm c[lm] R_lm(x, y, z): the gradient of one
+// combination of the solid harmonics above, from the partial derivatives of
+// their polynomial forms (cheaper than carrying the full gradient through
+// every harmonic when only this contraction is needed).
+template <typename R, int L>
+__device__ __forceinline__ void solid_harmonics_grad(R x, R y, R z, const R* c, R* g) {
+    constexpr double C1 = 0.4886025119029199;
+    constexpr double C2A = 1.0925484305920792, C20 = 0.31539156525252005, C22 = 0.5462742152960396;
+    constexpr double C33 = 0.5900435899266435, C32 = 2.890611442640554, C31 = 0.4570457994644658;
+    constexpr double C30 = 0.3731763325901154, C32B = 1.445305721320277;
+    constexpr double C44 = 2.5033429417967046, C43 = 1.7701307697799304, C42 = 0.9461746957575601;
+    constexpr double C41 = 0.6690465435572892, C40 = 0.10578554691520431, C42B = 0.47308734787878004;
+    constexpr double C44B = 0.6258357354491761;
+    R gx = R(C1) * c[2], gy = R(C1) * c[0], gz = R(C1) * c[1];
+    if (L >= 2) {
+        const R a3 = R(C2A) * c[3], a4 = R(C2A) * c[4], a5 = R(C20) * c[5], a6 = R(C2A) * c[6], a7 = R(C22) * c[7];
+        gx += a3 * y + a6 * z + R(2) * x * (a7 - a5);
+        gy += a3 * x + a4 * z - R(2) * y * (a5 + a7);
+        gz += a4 * y + a6 * x + R(4) * z * a5;
+    }
+    if (L >= 3) {
+        const R x2 = x * x, y2 = y * y, z2 = z * z, xy = x * y, xz = x * z, yz = y * z;
+        const R a8 = R(C33) * c[8], a9 = R(C32) * c[9], a10 = R(C31) * c[10], a11 = R(C30) * c[11];
+        const R a12 = R(C31) * c[12], a13 = R(C32B) * c[13], a14 = R(C33) * c[14];
+        const R t3 = R(4) * z2 - x2 - y2;  // 5z^2 - r^2
+        gx += R(6) * xy * a8 + yz * a9 - R(2) * xy * a10 - R(6) * xz * a11 + (t3 - R(2) * x2) * a12 +
+              R(2) * xz * a13 + R(3) * (x2 - y2) * a14;
+        gy += R(3) * (x2 - y2) * a8 + xz * a9 + (t3 - R(2) * y2) * a10 - R(6) * yz * a11 - R(2) * xy * a12 -
+              R(2) * yz * a13 - R(6) * xy * a14;
+        gz += xy * a9 + R(8) * yz * a10 + R(3) * (R(2) * z2 - x2 - y2) * a11 + R(8) * xz * a12 + (x2 - y2) * a13;
+        if (L >= 4) {
+            const R a15 = R(C44) * c[15], a16 = R(C43) * c[16], a17 = R(C42) * c[17], a18 = R(C41) * c[18];
+            const R a19 = R(C40) * c[19], a20 = R(C41) * c[20], a21 = R(C42B) * c[21], a22 = R(C43) * c[22];
+            const R a23 = R(C44B) * c[23];
+            const R r2 = x2 + y2 + z2, d = x2 - y2;
+            const R t42 = R(6) * z2 - x2 - y2;            // 7z^2 - r^2
+            const R t41 = R(4) * z2 - R(3) * (x2 + y2);   // 7z^2 - 3r^2
+            const R p19 = R(12) * r2 - R(60) * z2;
+            gx += (R(3) * x2 - y2) * y * a15 + R(6) * xy * z * a16 + y * (t42 - R(2) * x2) * a17 - R(6) * xy * z * a18 +
+                  x * p19 * a19 + z * (t41 - R(6) * x2) * a20 + R(2) * x * (t42 - d) * a21 +
+                  R(3) * d * z * a22 + R(4) * x * (x2 - R(3) * y2) * a23;
+            gy += x * (x2 - R(3) * y2) * a15 + R(3) * d * z * a16 + x * (t42 - R(2) * y2) * a17 +
+                  z * (t41 - R(6) * y2) * a18 + y * p19 * a19 - R(6) * xy * z * a20 - R(2) * y * (t42 + d) * a21 -
+                  R(6) * xy * z * a22 + R(4) * y * (y2 - R(3) * x2) * a23;
+            gz += y * (R(3) * x2 - y2) * a16 + R(12) * xy * z * a17 + y * (t41 + R(8) * z2) * a18 +
+                  z * (R(80) * z2 - R(48) * r2) * a19 + x * (t41 + R(8) * z2) * a20 + R(12) * d * z * a21 +
+                  x * (x2 - R(3) * y2) * a22;
+        }
+    }
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
 }
 
 template <int LM>

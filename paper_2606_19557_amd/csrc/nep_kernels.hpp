@@ -295,10 +295,6 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
             if (k < ang) {
                 R fa[KA], fap[KA];
                 cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
-                const G3<R> gx = {u[0], R(1), R(0), R(0)}, gy = {u[1], R(0), R(1), R(0)},
-                            gz = {u[2], R(0), R(0), R(1)};
-                G3<R> Yg[LM];
-                solid_harmonics<G3<R>, R, Sh::L>(gx, gy, gz, Yg);
                 R c[LM], cp[LM];
 #pragma unroll
                 for (int lm = 0; lm < LM; ++lm) c[lm] = cp[lm] = R(0);
@@ -316,15 +312,16 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
                         cp[lm] += Bk[n * LM + lm] * gp;
                     }
                 }
-                R sY = R(0), lY = R(0), G[3] = {R(0), R(0), R(0)};
+                // G = grad_u sum_lm c_lm Y_lm(u); Y_lm is homogeneous of degree l, so
+                // u . G = sum_lm l c_lm Y_lm (Euler) and the tangential part of
+                // the gradient is G - (u . G) u.
+                R Y[LM], G[3];
+                solid_harmonics<R, R, Sh::L>(u[0], u[1], u[2], Y);
+                R sY = R(0);
 #pragma unroll
-                for (int lm = 0; lm < LM; ++lm) {
-                    sY += cp[lm] * Yg[lm].v;
-                    lY += R(lm_degree<LM>(lm)) * c[lm] * Yg[lm].v;
-                    G[0] += c[lm] * Yg[lm].x;
-                    G[1] += c[lm] * Yg[lm].y;
-                    G[2] += c[lm] * Yg[lm].z;
-                }
+                for (int lm = 0; lm < LM; ++lm) sY += cp[lm] * Y[lm];
+                solid_harmonics_grad<R, Sh::L>(u[0], u[1], u[2], c, G);
+                const R lY = u[0] * G[0] + u[1] * G[1] + u[2] * G[2];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) hv[d] += sY * u[d] + (G[d] - lY * u[d]) * ir;
             }
