@@ -71,7 +71,7 @@ typedef struct {
     int32_t team_descriptor;   /* lanes per atom in the descriptor sweep: 4, 8 or 16 (default 8) */
     int32_t team_force;        /* lanes per atom in the force sweep and force gather (default 8) */
     int32_t team_tangent;      /* lanes per atom in the tangent sweep (default 8) */
-    int32_t team_coeff_grad;   /* lanes per atom in the angular coefficient-gradient sweep (default 8) */
+    int32_t team_coeff_grad;   /* lanes per atom in the angular coefficient-gradient sweep: 4, 8, 16 or 32 (default 8) */
     int32_t coeff_grad_blocks; /* grid cap of that sweep = its FP64 partial rows, 1..65536 (default 2048) */
     int32_t outer_chunk;       /* atoms per work item of the network/radial outer products, 8..4096 (default 64) */
     int32_t network;           /* per-species network passes: 1 = matrix-core tiles of 32 atoms (16 in FP64),
@@ -218,8 +218,8 @@ nep_status nep_backward(const nep_model* model, const void* theta, const void* q
 /* Autotuner of the launch plan (the tiling choice of the packed batch). Times
  * nep_loss_and_grad on this batch under candidate plans, `repeats` timed runs
  * each after one warm-up, with HIP events around every kernel launch:
- *   phase 1: team sizes 4, 8, 16 in all four pair sweeps; each sweep kernel
- *            keeps its fastest;
+ *   phase 1: team sizes 4, 8, 16 in all four pair sweeps (and 32 in the
+ *            coefficient-gradient sweep); each sweep kernel keeps its fastest;
  *   phase 2: (coeff_grad_blocks, outer_chunk) pairs, chosen by the summed time
  *            of the two kernels and the reductions that read their rows;
  *   phase 3: the two network implementations, by their summed time.

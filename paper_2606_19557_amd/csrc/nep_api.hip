@@ -112,8 +112,10 @@ nep_status resolve_plan(const nep_plan* p, Plan* out) {
         int* dst[4] = {&q.team_desc, &q.team_force, &q.team_tangent, &q.team_cg};
         for (int k = 0; k < 4; ++k) {
             if (teams[k] == 0) continue;
-            if (teams[k] != 4 && teams[k] != 8 && teams[k] != 16)
-                return fail(NEP_ERR_INVALID_ARG, "plan team size %d is not 4, 8 or 16", teams[k]);
+            const bool wide = k == 3 && teams[k] == 32;  // the coefficient sweep also takes 32
+            if (teams[k] != 4 && teams[k] != 8 && teams[k] != 16 && !wide)
+                return fail(NEP_ERR_INVALID_ARG, "plan team size %d is not 4, 8 or 16%s", teams[k],
+                            k == 3 ? " or 32" : "");
             *dst[k] = teams[k];
         }
         if (p->coeff_grad_blocks != 0) {
@@ -554,6 +556,17 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
                     *field[q] = cand[k];
                 }
             }
+        }
+        // the coefficient sweep alone also tries 32-lane teams
+        nep_plan p = best;
+        p.team_coeff_grad = 32;
+        std::map<std::string, double> avg;
+        nep_status s = measure(p, &avg);
+        if (fits(s)) {
+            if (get(avg, "angular_coeff_grad") < tb[3]) best.team_coeff_grad = 32;
+        } else if (!skippable(s)) {
+            g_prof_on = was_on;
+            return s;
         }
     }
     // phase 2: grid of the coefficient sweep and chunk of the outer products

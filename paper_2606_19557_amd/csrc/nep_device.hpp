@@ -349,7 +349,9 @@ struct MomentExchange {
 #pragma unroll
         for (int lm = 0; lm < LM; ++lm) mine[NA + lm] = Y[lm];
         wave_fence();
-#pragma unroll
+        // unrolled by at most 8 pairs: wide teams would otherwise hold the
+        // loads of every pair of the batch in registers at once
+#pragma unroll 8
         for (int q = 0; q < S; ++q) {
             const R* src = team_buf + q * SLOT;
             R yv[OWN];

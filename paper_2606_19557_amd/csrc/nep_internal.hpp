@@ -128,6 +128,14 @@ template <class F>
 nep_status with_team(int s, F&& f) {
     return with_team_size<nep_status>(s, static_cast<F&&>(f));
 }
+// the coefficient-gradient sweep also runs with 32-lane teams (its per-team
+// LDS block makes wide teams the way to fit more waves per CU for large moment
+// blocks with many angular neighbours)
+template <typename T, class F>
+T with_cg_team_size(int s, F&& f) {
+    if (s == 32) return f(std::integral_constant<int, 32>{});
+    return with_team_size<T>(s, static_cast<F&&>(f));
+}
 
 // Per-shape pipeline (forward / loss+grad / backward / descriptors).
 using ShapeFn = nep_status (*)(const Ctx&);

@@ -21,6 +21,23 @@ __device__ __forceinline__ R load_theta(const R* __restrict__ th, long idx) {
     return th[idx];
 }
 
+// Occupancy requests of the pair sweeps (waves per SIMD that their registers
+// must allow; 1 leaves the allocation unconstrained). FP32 sweeps of large
+// moment blocks (N_A x 24 > 120) come out a few registers above 256, i.e.
+// one wave per SIMD; asking for two costs at most a small spill. The tangent
+// sweep of small blocks with teams of 8 fits 3 waves with 28 bytes per lane
+// spilled, which measures faster than 2 waves without. The coefficient
+// sweep with 16- or 32-lane teams is a few registers above 3 waves. FP64
+// sweeps would spill hundreds of bytes per lane and are left alone.
+template <typename R, class Sh, int S>
+struct SweepWaves {
+    static constexpr bool f32 = sizeof(R) == 4;
+    static constexpr bool big = Sh::NA * Sh::LM > 120;
+    static constexpr int descriptor = (f32 && big) ? 2 : 1;
+    static constexpr int tangent = !f32 ? 1 : big ? 2 : S == 8 ? 3 : 1;
+    static constexpr int coeff_grad = (f32 && S >= 16) ? 3 : 1;
+};
+
 // ------------------------------------------------------------------ descriptor
 
 // q (radial, Eqs. 15-16; angular invariants, Eqs. 19-20 and the 4/5-body
@@ -29,7 +46,7 @@ __device__ __forceinline__ R load_theta(const R* __restrict__ th, long idx) {
 // Angular pairs are processed S at a time by the team and their (g_n, Y_lm)
 // exchanged through LDS; each lane owns the moments lm = lane + S*o.
 template <typename R, class Sh, int S>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::descriptor))
 k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
              const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
              R* __restrict__ q_out, R* __restrict__ A_out, R* __restrict__ S0_out) {
@@ -381,16 +398,6 @@ k_force_gather(int Na, const int64_t* __restrict__ row, const int* __restrict__ 
     if (live && lane < 3) F_out[(long)i * 3 + lane] = Fown[(long)i * 3 + lane] + (lane == 0 ? f[0] : (lane == 1 ? f[1] : f[2]));
 }
 
-// Occupancy request of the tangent sweep (waves per SIMD its registers must
-// allow). For small moment blocks (N_A x 24 <= 120) with teams of 8 the
-// compiler fits 3 waves with 28 bytes per lane spilled, which measures faster
-// than 2 waves without; other team sizes and larger shapes would spill
-// hundreds of bytes per lane, so they keep the unconstrained allocation.
-template <class Sh, int S>
-struct SweepWaves {
-    static constexpr int tangent = (Sh::NA * Sh::LM <= 120 && S == 8) ? 3 : 1;
-};
-
 // ----------------------------------------------------------------- tangent
 
 // Directional derivative of the descriptor along v_ij = u_i - u_j - U_s^T r_ij:
@@ -398,7 +405,7 @@ struct SweepWaves {
 // and S1[b][k] = sum_{j in b} (v.r^) f_k'. Angular pairs go through the team
 // exchange (two terms per pair); each lane owns the moments lm = lane + S*o.
 template <typename R, class Sh, int S>
-__global__ void __launch_bounds__(kBlock, (SweepWaves<Sh, S>::tangent))
+__global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::tangent))
 k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types,
           const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row, const int* __restrict__ seg,
           const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar, const double* __restrict__ Ubar,
@@ -598,17 +605,22 @@ struct CoeffGradSmem {
     // distinct banks
     static constexpr int WORDS = 2 * NA * LM * int(sizeof(R)) / 4;
     static constexpr int BQ_STRIDE = (WORDS + ((8 - WORDS) % 32 + 32) % 32) * 4 / int(sizeof(R));
+    // per-team region holding the exchange during a segment's pair loop and
+    // the team's N_A x K_A sums after it; grown past the exchange by whole
+    // 128-byte steps, so team regions keep the exchange's bank pattern
+    static constexpr int NK = NA * KA, STEP = 128 / int(sizeof(R));
+    static constexpr int REGION =
+        X::TEAM_FLOATS >= NK ? X::TEAM_FLOATS : X::TEAM_FLOATS + (NK - X::TEAM_FLOATS + STEP - 1) / STEP * STEP;
     __host__ __device__ static constexpr size_t align16(size_t n) { return (n * sizeof(R) + 15) / 16 * 16 / sizeof(R); }
-    // offsets (in R) of the regions: G, team slots, Bp/Q blocks, exchange
-    __host__ __device__ static size_t off_slot(int T) { return align16(size_t(T) * T * NA * KA); }
-    __host__ __device__ static size_t off_bq(int T) { return align16(off_slot(T) + size_t(TEAMS) * NA * KA); }
+    // offsets (in R) of the regions: G, Bp/Q blocks, team regions
+    __host__ __device__ static size_t off_bq(int T) { return align16(size_t(T) * T * NK); }
     __host__ __device__ static size_t off_x(int T) { return off_bq(T) + size_t(TEAMS) * BQ_STRIDE; }
-    __host__ __device__ static size_t bytes(int T) { return sizeof(R) * (off_x(T) + size_t(TEAMS) * X::TEAM_FLOATS) + sizeof(int) * TEAMS; }
+    __host__ __device__ static size_t bytes(int T) { return sizeof(R) * (off_x(T) + size_t(TEAMS) * REGION) + sizeof(int) * TEAMS; }
 };
 static_assert(CoeffGradSmem<float, Shape<9, 9, 7, 5, 4, 0, 0>, 8>::BQ_STRIDE % 4 == 0, "vector alignment");
 
 template <typename R, class Sh, int S>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::coeff_grad))
 k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
                      const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
                      const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ A_in,
@@ -624,15 +636,14 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
     const int T = dm.T;
     const int G_len = T * T * NK;
     R* G = reinterpret_cast<R*>(smem_raw);
-    R* slot = G + SM::off_slot(T);            // [TEAMS][NK]
     R* BQ = G + SM::off_bq(T);                // [TEAMS][BQ_STRIDE]: Bp[NA][LM], Q[NA][LM]
-    R* xb = G + SM::off_x(T);                 // [TEAMS][exchange]
-    int* team_type = reinterpret_cast<int*>(xb + TEAMS * X::TEAM_FLOATS);
+    R* xb = G + SM::off_x(T);                 // [TEAMS][REGION]: exchange, then the team's sums
+    int* team_type = reinterpret_cast<int*>(xb + TEAMS * SM::REGION);
     for (int x = threadIdx.x; x < G_len; x += kBlock) G[x] = R(0);
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     R* myBp = BQ + team * SM::BQ_STRIDE;
     R* myQ = myBp + NA * LM;
-    R* tbuf = xb + team * X::TEAM_FLOATS;
+    R* tbuf = xb + team * SM::REGION;
     const R rcA = R(dm.rcA), irA = R(1.0 / dm.rcA);
     const int tiles = (Na + TEAMS - 1) / TEAMS;
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -726,12 +737,12 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
 #pragma unroll
                 for (int o = 0; o < OWN; ++o) {
                     const int kk = lane + S * o;
-                    if (kk < KA) slot[team * NK + n * KA + kk] = live ? acc[n][o] : R(0);
+                    if (kk < KA) tbuf[n * KA + kk] = live ? acc[n][o] : R(0);
                 }
             if (lane == 0) team_type[team] = a;
             __syncthreads();
             for (int x = threadIdx.x; x < NK; x += kBlock)
-                for (int tm = 0; tm < TEAMS; ++tm) G[(team_type[tm] * T + b) * NK + x] += slot[tm * NK + x];
+                for (int tm = 0; tm < TEAMS; ++tm) G[(team_type[tm] * T + b) * NK + x] += xb[tm * SM::REGION + x];
             __syncthreads();
         }
     }

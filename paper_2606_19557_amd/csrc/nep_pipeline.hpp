@@ -29,7 +29,7 @@ nep_status run_shape(const Ctx& c) {
     nep_status rs = NEP_OK;
 
     // LDS of the angular-coefficient gradient block (dynamic; <= one CU's 160 KB)
-    const size_t cg_shm = with_team_size<size_t>(c.plan.team_cg, [&](auto S_) {
+    const size_t cg_shm = with_cg_team_size<size_t>(c.plan.team_cg, [&](auto S_) {
         return CoeffGradSmem<R, Sh, decltype(S_)::value>::bytes(dm.T);
     });
     if (c.mode == Mode::LossGrad || c.mode == Mode::Backward) {
@@ -105,7 +105,7 @@ nep_status run_shape(const Ctx& c) {
             NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
                        qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e),
                        Wr(L.t), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
-        if ((rs = with_team(c.plan.team_cg, [&](auto S_) -> nep_status {
+        if ((rs = with_cg_team_size<nep_status>(c.plan.team_cg, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
                 if (cg_shm > 64 * 1024)
                     NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad<R, Sh, S>),

@@ -107,7 +107,10 @@ def test_plan_validation_and_workspace():
     small = nep.nep_workspace_size(m.with_plan(nep.Plan(outer_chunk=256, coeff_grad_blocks=64)), 10, 5000, 200000)
     big = nep.nep_workspace_size(m.with_plan(nep.Plan(outer_chunk=8)), 10, 5000, 200000)
     assert small < base < big
-    for bad in (nep.Plan(team_descriptor=5), nep.Plan(team_force=32), nep.Plan(coeff_grad_blocks=-1),
+    # 32-lane teams exist only in the coefficient-gradient sweep
+    assert nep.nep_workspace_size(m.with_plan(nep.Plan(team_coeff_grad=32)), 10, 5000, 200000) > 0
+    for bad in (nep.Plan(team_descriptor=5), nep.Plan(team_force=32), nep.Plan(team_tangent=32),
+                nep.Plan(team_descriptor=32), nep.Plan(team_coeff_grad=64), nep.Plan(coeff_grad_blocks=-1),
                 nep.Plan(outer_chunk=4), nep.Plan(outer_chunk=5000), nep.Plan(network=3)):
         with pytest.raises(nep.NepError) as e:
             nep.nep_workspace_size(m.with_plan(bad), 10, 5000, 200000)

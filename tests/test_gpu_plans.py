@@ -18,6 +18,7 @@ PLANS = [
     N.Plan(16, 16, 16, 16, 4096, 256, 2),
     N.Plan(4, 16, 8, 16, 1, 8, 1),
     N.Plan(16, 4, 16, 8, 7, 100, 2),
+    N.Plan(8, 8, 8, 32, 300, 64, 1),
 ]
 
 
@@ -65,8 +66,9 @@ def test_autotune_returns_valid_plan():
     qs = torch.tensor(s, dtype=torch.float32, device="cuda")
     targets = N.Targets(*tg)
     plan = N.nep_autotune(model, theta, qs, gb, nb, targets, repeats=2)
-    for k in ("team_descriptor", "team_force", "team_tangent", "team_coeff_grad"):
+    for k in ("team_descriptor", "team_force", "team_tangent"):
         assert getattr(plan, k) in (4, 8, 16)
+    assert plan.team_coeff_grad in (4, 8, 16, 32)
     assert plan.coeff_grad_blocks in (512, 1024, 2048, 4096) and plan.outer_chunk in (32, 64, 128, 256)
     assert plan.network in (1, 2)
     tuned = model.with_plan(plan)
