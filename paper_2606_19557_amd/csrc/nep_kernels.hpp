@@ -349,6 +349,10 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
                 ho.z = -hv[2];
                 ho.w = R(0);
                 h_in[q] = ho;  // -dE_i/dr_ij is the pair's contribution to F_j
+            } else {
+                // no reverse pair (|r| at the cutoff in one direction only):
+                // nothing else writes this pair's own slot
+                h_in[p + k] = Rec<R>{};
             }
             const R rv[3] = {pr.x, pr.y, pr.z};
 #pragma unroll
@@ -376,18 +380,20 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
 
 // F_i = (own-direction sum) + sum_{p in row i} h_in[p]: team of S lanes per
 // atom over its (contiguous) row, team sum in fixed shuffle order. Slots of
-// pairs without a reverse partner were never written and are skipped.
+// pairs without a reverse partner hold zeros (written by the force sweep).
 template <typename R, int S>
 __global__ void __launch_bounds__(kBlock)
-k_force_gather(int Na, const int64_t* __restrict__ row, const int* __restrict__ reverse,
-               const Rec<R>* __restrict__ h_in, const R* __restrict__ Fown, R* __restrict__ F_out) {
+k_force_gather(int Na, const int64_t* __restrict__ row, const Rec<R>* __restrict__ h_in,
+               const R* __restrict__ Fown, R* __restrict__ F_out) {
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     const int i = blockIdx.x * (kBlock / S) + team;
     const bool live = i < Na;
     const int64_t p0 = live ? row[i] : 0, p1 = live ? row[i + 1] : 0;
     R f[3] = {R(0), R(0), R(0)};
+    // every slot is written by the force sweep (zero for unpaired pairs), so
+    // the loads are unconditional and several are in flight at once
+#pragma unroll 4
     for (int64_t p = p0 + lane; p < p1; p += S) {
-        if (reverse[p] < 0) continue;  // unpaired (|r| at the cutoff): slot never written
         const Rec<R> a = h_in[p];
         f[0] += a.x;
         f[1] += a.y;

@@ -72,7 +72,7 @@ nep_status run_shape(const Ctx& c) {
                            c.types, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e),
                            reinterpret_cast<Rec<R>*>(Wr(L.h)), Wr(L.Fown), Wr(L.Wat));
                 NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, Na,
-                           c.row, c.reverse, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
+                           c.row, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
                 return NEP_OK;
             })))
             return rs;

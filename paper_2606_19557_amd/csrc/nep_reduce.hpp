@@ -9,20 +9,6 @@ namespace nep {
 
 constexpr int kRedBlock = 256;
 
-// Block-wide sum of a double (wave64 shuffles, then one value per wave in LDS).
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) scratch[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += scratch[k];
-    return t;  // valid in thread 0
-}
-
 // One block per structure: E_s = sum E_i and W_s = sum of per-atom virials in
 // double. With `loss` set: the loss pieces of the structure and the seeds
 //   ebar_s = dL/dE_s = 2 lam_e (E_s - E*_s) / (N_s N_a^s^2),
@@ -37,41 +23,61 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
             double lam_e, double lam_f, double lam_v, double* __restrict__ E_out, double* __restrict__ W_out,
             double* __restrict__ ebar, double* __restrict__ Ubar, R* __restrict__ ubar,
             double* __restrict__ lossp) {
-    __shared__ double scratch[kRedBlock / 64];
-    __shared__ double res[11];
+    // E, W[9], the force residual and the number of labelled structures
+    constexpr int NV = 12, WAVES = kRedBlock / 64;
+    __shared__ double part[WAVES][NV];
     const int s = blockIdx.x;
     const long a0 = off[s], a1 = off[s + 1];
     const double na = double(a1 - a0);
-    double acc[11];
+    // the structure's targets are loaded first, so their latency overlaps the sums
+    double Ets = 0.0, Wts[9];
+    bool hv = true;
 #pragma unroll
-    for (int c = 0; c < 11; ++c) acc[c] = 0.0;
+    for (int c = 0; c < 9; ++c) Wts[c] = 0.0;
+    if (loss && threadIdx.x == 0) {
+        Ets = Et[s];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Wts[c] = Wt[s * 9 + c];
+        hv = has_v ? has_v[s] != 0 : true;
+    }
+    double acc[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] = 0.0;
     const double cf = 2.0 * lam_f / (3.0 * double(Na));
     for (long i = a0 + threadIdx.x; i < a1; i += kRedBlock) {
-        const R fi[3] = {F[i * 3], F[i * 3 + 1], F[i * 3 + 2]};
         acc[0] += double(E_at[i]);
 #pragma unroll
         for (int c = 0; c < 9; ++c) acc[1 + c] += double(W_at[i * 9 + c]);
         if (loss) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const double r = double(fi[d]) - double(Ft[i * 3 + d]);
+                const double r = double(F[i * 3 + d]) - double(Ft[i * 3 + d]);
                 acc[10] += r * r;
                 ubar[i * 3 + d] = R(cf * r);
             }
         }
     }
-    // number of structures with a virial label
-    double nv = 0.0;
-    if (loss) {
-        for (int t = threadIdx.x; t < Ns; t += kRedBlock) nv += has_v ? double(has_v[t] != 0) : 1.0;
-    }
+    if (loss)
+        for (int t = threadIdx.x; t < Ns; t += kRedBlock) acc[11] += has_v ? double(has_v[t] != 0) : 1.0;
+    // wave sums by shuffles, one barrier, then the waves' sums in wave order
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
-    for (int c = 0; c < 11; ++c) {
-        const double t = block_sum(acc[c], scratch);
-        if (threadIdx.x == 0) res[c] = t;
+    for (int c = 0; c < NV; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (l == 0) part[w][c] = v;
     }
-    const double Nv = loss ? block_sum(nv, scratch) : 0.0;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double res[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) t += part[k][c];
+        res[c] = t;
+    }
     const double E = res[0];
     if (E_out) E_out[s] = E;
     if (W_out)
@@ -85,14 +91,14 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
         lossp[s * 3 + 2] = 0.0;
         return;
     }
-    const double dE = E - Et[s];
+    const double Nv = res[11];
+    const double dE = E - Ets;
     ebar[s] = 2.0 * lam_e * dE / (double(Ns) * na * na);
     lossp[s * 3 + 0] = (dE / na) * (dE / na) / double(Ns);
     lossp[s * 3 + 1] = res[10] / (3.0 * double(Na));
-    const bool hv = has_v ? has_v[s] != 0 : true;
     double dv = 0.0;
     for (int c = 0; c < 9; ++c) {
-        const double dw = res[1 + c] - Wt[s * 9 + c];
+        const double dw = res[1 + c] - Wts[c];
         if (hv && Nv > 0.0) {
             dv += (dw / na) * (dw / na) / (9.0 * Nv);
             Ubar[s * 9 + c] = 2.0 * lam_v * dw / (9.0 * Nv * na * na);
@@ -145,13 +151,19 @@ k_reduce_stage(Dims dm, int NRKR, const double* __restrict__ outer_part, int out
             col = (p - dm.offN) % net_w;
         }
         const int step = waves * G;
+        // unconditional loads in unrolled loops: the rows' loads are in
+        // flight together instead of one round trip per row
         if (col >= 0) {
+            const double tag = double(a);
+#pragma unroll 4
             for (int r = g * waves + wave; r < outer_rows; r += step) {
                 const double* row = outer_part + (long)r * (W1 + 1);
-                if (row[0] == double(a)) s += row[1 + col];
+                const double t = row[0], v = row[1 + col];
+                s += t == tag ? v : 0.0;
             }
         } else {
             const long angw = dm.offN - dm.offA;
+#pragma unroll 8
             for (int r = g * waves + wave; r < ang_rows; r += step) s += ang_part[(long)r * angw + (p - dm.offA)];
         }
     }
@@ -171,35 +183,51 @@ __global__ void __launch_bounds__(kRedBlock)
 k_final_reduce(Dims dm, int Ns, const int64_t* __restrict__ off, const double* __restrict__ stage, int G,
                const double* __restrict__ ebar, const double* __restrict__ lossp, double lam_e, double lam_f,
                double lam_v, R* __restrict__ grad, double* __restrict__ loss) {
-    __shared__ double scratch[kRedBlock / 64];
     const long p = (long)blockIdx.x * kRedBlock + threadIdx.x;
     if (p < dm.offB1) {
         double t = 0.0;
+#pragma unroll 8
         for (int g = 0; g < G; ++g) t += stage[(long)g * dm.offB1 + p];
         grad[p] = R(t);
     }
     if (blockIdx.x != 0) return;
-    double sb = 0.0, dE = 0.0, dF = 0.0, dV = 0.0;
+    // -sum_s N_a^s ebar_s and the three loss parts: wave sums, one barrier,
+    // then the waves' sums in wave order
+    constexpr int WAVES = kRedBlock / 64;
+    __shared__ double part[WAVES][4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < Ns; t += kRedBlock) {
-        sb -= double(off[t + 1] - off[t]) * ebar[t];
+        acc[0] -= double(off[t + 1] - off[t]) * ebar[t];
         if (loss) {
-            dE += lossp[t * 3 + 0];
-            dF += lossp[t * 3 + 1];
-            dV += lossp[t * 3 + 2];
+            acc[1] += lossp[t * 3 + 0];
+            acc[2] += lossp[t * 3 + 1];
+            acc[3] += lossp[t * 3 + 2];
         }
     }
-    sb = block_sum(sb, scratch);
-    if (threadIdx.x == 0) grad[dm.offB1] = R(sb);
-    if (!loss) return;
-    dE = block_sum(dE, scratch);
-    dF = block_sum(dF, scratch);
-    dV = block_sum(dV, scratch);
-    if (threadIdx.x == 0) {
-        loss[0] = lam_e * dE + lam_f * dF + lam_v * dV;
-        loss[1] = dE;
-        loss[2] = dF;
-        loss[3] = dV;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (l == 0) part[w][c] = v;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double res[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) t += part[k][c];
+        res[c] = t;
+    }
+    grad[dm.offB1] = R(res[0]);
+    if (!loss) return;
+    loss[0] = lam_e * res[1] + lam_f * res[2] + lam_v * res[3];
+    loss[1] = res[1];
+    loss[2] = res[2];
+    loss[3] = res[3];
 }
 
 // One Adam/AMSGrad step (Eqs. 8-13), elementwise.
