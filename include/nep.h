@@ -76,7 +76,8 @@ typedef struct {
     int32_t outer_chunk;       /* atoms per work item of the network/radial outer products, 8..4096 (default 64) */
     int32_t network;           /* per-species network passes: 1 = matrix-core tiles of 32 atoms (16 in FP64),
                                   2 = one lane per atom in 64-atom wavefronts, weights as wave-uniform
-                                  (scalar) operands; default 1 */
+                                  (scalar) operands; 3 = inside the descriptor and tangent sweeps, each
+                                  atom's team splitting the hidden units (no network launches); default 1 */
 } nep_plan;
 
 /* Model hyper-parameters (the model keys of the paper's input file, Table I). */
@@ -222,7 +223,8 @@ nep_status nep_backward(const nep_model* model, const void* theta, const void* q
  *            coefficient-gradient sweep); each sweep kernel keeps its fastest;
  *   phase 2: (coeff_grad_blocks, outer_chunk) pairs, chosen by the summed time
  *            of the two kernels and the reductions that read their rows;
- *   phase 3: the two network implementations, by their summed time.
+ *   phase 3: the three network implementations, by the summed time of the
+ *            network kernels and the sweeps that host the fused variant.
  * Candidates whose workspace exceeds ws_bytes or whose LDS exceeds a CU are
  * skipped. Writes the chosen plan to *plan_out (host); model->plan is ignored.
  * The arguments are those of nep_loss_and_grad (loss and grad are overwritten).

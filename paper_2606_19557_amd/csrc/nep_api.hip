@@ -129,8 +129,8 @@ nep_status resolve_plan(const nep_plan* p, Plan* out) {
             q.outer_chunk = p->outer_chunk;
         }
         if (p->network != 0) {
-            if (p->network != 1 && p->network != 2)
-                return fail(NEP_ERR_INVALID_ARG, "plan network %d is not 1 or 2", p->network);
+            if (p->network < 1 || p->network > 3)
+                return fail(NEP_ERR_INVALID_ARG, "plan network %d is not 1, 2 or 3", p->network);
             q.network = p->network;
         }
     }
@@ -598,7 +598,7 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
     {
         double tb = 1e300;
         nep_plan keep = best;
-        for (int k = 1; k <= 2; ++k) {
+        for (int k = 1; k <= 3; ++k) {
             nep_plan p = best;
             p.network = k;
             std::map<std::string, double> avg;
@@ -608,7 +608,9 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
                 g_prof_on = was_on;
                 return s;
             }
-            const double t = get(avg, "network_forward") + get(avg, "network_backward");
+            // the fused network (3) adds to the descriptor and tangent sweeps
+            const double t = get(avg, "network_forward") + get(avg, "network_backward") + get(avg, "descriptor") +
+                             get(avg, "tangent") + get(avg, "outer_grad");
             if (t < tb) {
                 tb = t;
                 keep = p;

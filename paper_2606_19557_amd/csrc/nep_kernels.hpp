@@ -38,6 +38,119 @@ struct SweepWaves {
     static constexpr int coeff_grad = (f32 && S >= 16) ? 3 : 1;
 };
 
+// ------------------------------------------------ network inside the sweeps
+
+// The per-species network of one atom split over its team (the fused plan):
+// lane l takes hidden units mu = l, l + S, ... and the team sums the rest.
+// Per-unit rows (t, alpha, beta, gamma) are indexed by atom.
+
+// Eqs. 2-3: E_i = sum_mu w1 tanh(W0 (s q) - b0) - b1 and e = dE_i/dq; every
+// lane holds the atom's descriptor qv.
+template <typename R, int D, int S>
+__device__ __forceinline__ void team_network_forward(int lane, const Dims& dm, const R* __restrict__ theta, int a,
+                                                     const R* __restrict__ qscale, const R (&qv)[D], long i,
+                                                     R* __restrict__ E_out, R* __restrict__ e_out,
+                                                     R* __restrict__ t_out) {
+    const int H = dm.H;
+    const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
+    const R* __restrict__ b0 = W0 + (long)H * D;
+    const R* __restrict__ w1 = b0 + H;
+    R qs[D], ev[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        qs[v] = qscale[v] * qv[v];
+        ev[v] = R(0);
+    }
+    R E = R(0);
+    // two hidden units per step (mu and mu + S), so that both weight rows
+    // are in flight together; a missing second unit reads the first's row
+    for (int mu = lane; mu < H; mu += 2 * S) {
+        const bool two = mu + S < H;
+        const int mu2 = two ? mu + S : mu;
+        const R* __restrict__ w = W0 + (long)mu * D;
+        const R* __restrict__ w2 = W0 + (long)mu2 * D;
+        R acc = -b0[mu], acc2 = -b0[mu2];
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            acc += w[v] * qs[v];
+            acc2 += w2[v] * qs[v];
+        }
+        const R t = tanh_<R>(acc), t2 = tanh_<R>(acc2);
+        const R wm = w1[mu], wm2 = two ? w1[mu2] : R(0);
+        E += wm * t + wm2 * t2;
+        const R c = wm * (R(1) - t * t), c2 = wm2 * (R(1) - t2 * t2);
+#pragma unroll
+        for (int v = 0; v < D; ++v) ev[v] += w[v] * c + w2[v] * c2;
+        t_out[i * H + mu] = t;
+        if (two) t_out[i * H + mu2] = t2;
+    }
+    E = team_sum<S>(E);
+#pragma unroll
+    for (int v = 0; v < D; ++v) ev[v] = team_sum<S>(ev[v]);
+    if (lane == 0) E_out[i] = E - theta[dm.offB1];
+#pragma unroll
+    for (int v = 0; v < D; ++v)
+        if (v % S == lane) e_out[i * D + v] = qscale[v] * ev[v];
+}
+
+// The Hessian-vector product and weight-gradient factors of the force/virial
+// adjoint for one atom (as the network backward pass): da = W0 (s dq),
+// alpha = w1 s'(ebar - 2 t da), beta = w1 s', gamma = ebar t + s' da,
+// abar = ebar e + s (W0^T (-2 w1 t s' da)); every lane holds dq.
+template <typename R, int D, int S>
+__device__ __forceinline__ void team_network_backward(int lane, const Dims& dm, const R* __restrict__ theta, int a,
+                                                      const R* __restrict__ qscale, const R (&dq)[D], R eb, long i,
+                                                      const R* __restrict__ e_in, const R* __restrict__ t_in,
+                                                      R* __restrict__ abar_out, R* __restrict__ alpha_out,
+                                                      R* __restrict__ beta_out, R* __restrict__ gamma_out) {
+    const int H = dm.H;
+    const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
+    const R* __restrict__ w1 = W0 + (long)H * D + H;
+    R dk[D], z[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+        dk[v] = qscale[v] * dq[v];
+        z[v] = R(0);
+    }
+    // the atom's e entries this lane writes abar for, loaded up front
+    constexpr int OWNV = (D + S - 1) / S;
+    R eo[OWNV];
+#pragma unroll
+    for (int o = 0; o < OWNV; ++o) eo[o] = lane + S * o < D ? e_in[i * D + lane + S * o] : R(0);
+    // two hidden units per step, as in the forward pass
+    for (int mu = lane; mu < H; mu += 2 * S) {
+        const bool two = mu + S < H;
+        const int mu2 = two ? mu + S : mu;
+        const R* __restrict__ w = W0 + (long)mu * D;
+        const R* __restrict__ w2 = W0 + (long)mu2 * D;
+        const R t = t_in[i * H + mu], t2 = t_in[i * H + mu2];
+        const R wm = w1[mu], wm2 = two ? w1[mu2] : R(0);
+        R da = R(0), da2 = R(0);
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            da += w[v] * dk[v];
+            da2 += w2[v] * dk[v];
+        }
+        const R sp = R(1) - t * t, sp2 = R(1) - t2 * t2;
+        alpha_out[i * H + mu] = wm * sp * (eb - R(2) * t * da);
+        beta_out[i * H + mu] = wm * sp;
+        gamma_out[i * H + mu] = eb * t + sp * da;
+        if (two) {
+            alpha_out[i * H + mu2] = wm2 * sp2 * (eb - R(2) * t2 * da2);
+            beta_out[i * H + mu2] = wm2 * sp2;
+            gamma_out[i * H + mu2] = eb * t2 + sp2 * da2;
+        }
+        const R c = R(-2) * wm * t * sp * da, c2 = R(-2) * wm2 * t2 * sp2 * da2;
+#pragma unroll
+        for (int v = 0; v < D; ++v) z[v] += w[v] * c + w2[v] * c2;
+    }
+#pragma unroll
+    for (int v = 0; v < D; ++v) z[v] = team_sum<S>(z[v]);
+#pragma unroll
+    for (int v = 0; v < D; ++v)
+        if (v % S == lane) abar_out[i * D + v] = eb * eo[v / S] + qscale[v] * z[v];
+}
+
 // ------------------------------------------------------------------ descriptor
 
 // q (radial, Eqs. 15-16; angular invariants, Eqs. 19-20 and the 4/5-body
@@ -45,11 +158,13 @@ struct SweepWaves {
 // radial basis sums S0[b][k] = sum_{j in b} f_k(r_ij) used by the gradient.
 // Angular pairs are processed S at a time by the team and their (g_n, Y_lm)
 // exchanged through LDS; each lane owns the moments lm = lane + S*o.
-template <typename R, class Sh, int S>
+// With NET the team then evaluates the atom's network (E_i, e_i, t_i).
+template <typename R, class Sh, int S, bool NET>
 __global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::descriptor))
 k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
              const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-             R* __restrict__ q_out, R* __restrict__ A_out, R* __restrict__ S0_out) {
+             R* __restrict__ q_out, R* __restrict__ A_out, R* __restrict__ S0_out, const R* __restrict__ qscale,
+             R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out) {
     constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D, L = Sh::L;
     using X = MomentExchange<R, NA, LM, S>;
     constexpr int OWN = X::OWN, TEAMS = kBlock / S;
@@ -150,31 +265,33 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
             q4v[n] = q4_value<R>(a2);
         }
     }
-    if (live) {
+    if (!live) return;
+    // the whole descriptor is known to every lane of the team
+    R qv[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            if (d % S != lane) continue;
-            R v;
-            if (d < NR) {
-                v = qR[d];
-            } else if (d < NR + L * NA) {
-                v = qA[d - NR];
-            } else if (Sh::H4 && d < NR + (L + 1) * NA) {
-                v = q4v[d - NR - L * NA];
-            } else {
-                const R P = qA[d - NR - (L + (Sh::H4 ? 1 : 0)) * NA];  // l = 1 three-body term
-                v = P * P;
-            }
-            q_out[(long)i * D + d] = v;
+    for (int d = 0; d < D; ++d) {
+        if (d < NR) {
+            qv[d] = qR[d];
+        } else if (d < NR + L * NA) {
+            qv[d] = qA[d - NR];
+        } else if (Sh::H4 && d < NR + (L + 1) * NA) {
+            qv[d] = q4v[d - NR - L * NA];
+        } else {
+            const R P = qA[d - NR - (L + (Sh::H4 ? 1 : 0)) * NA];  // l = 1 three-body term
+            qv[d] = P * P;
         }
-#pragma unroll
-        for (int n = 0; n < NA; ++n)
-#pragma unroll
-            for (int o = 0; o < OWN; ++o) {
-                const int lm = lane + S * o;
-                if (lm < LM) A_out[((long)i * NA + n) * LM + lm] = acc[n][o];
-            }
     }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (d % S == lane) q_out[(long)i * D + d] = qv[d];
+#pragma unroll
+    for (int n = 0; n < NA; ++n)
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int lm = lane + S * o;
+            if (lm < LM) A_out[((long)i * NA + n) * LM + lm] = acc[n][o];
+        }
+    if (NET) team_network_forward<R, D, S>(lane, dm, theta, a, qscale, qv, i, E_out, e_out, t_out);
 }
 
 // ------------------------------------------------ per-atom moment adjoints
@@ -410,12 +527,16 @@ k_force_gather(int Na, const int64_t* __restrict__ row, const Rec<R>* __restrict
 // dq (radial and invariants), dA[n][lm] = sum_j [g_n' (v.r^) Y_lm + g_n v.dY_lm],
 // and S1[b][k] = sum_{j in b} (v.r^) f_k'. Angular pairs go through the team
 // exchange (two terms per pair); each lane owns the moments lm = lane + S*o.
-template <typename R, class Sh, int S>
+// With NET the team then runs the atom's network Hessian-vector product.
+template <typename R, class Sh, int S, bool NET>
 __global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::tangent))
 k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types,
           const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row, const int* __restrict__ seg,
           const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar, const double* __restrict__ Ubar,
-          const R* __restrict__ A_in, R* __restrict__ dq_out, R* __restrict__ dA_out, R* __restrict__ S1_out) {
+          const R* __restrict__ A_in, R* __restrict__ dq_out, R* __restrict__ dA_out, R* __restrict__ S1_out,
+          const R* __restrict__ qscale, const double* __restrict__ ebar_s, const R* __restrict__ e_in,
+          const R* __restrict__ t_in, R* __restrict__ abar_out, R* __restrict__ alpha_out, R* __restrict__ beta_out,
+          R* __restrict__ gamma_out) {
     constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D, L = Sh::L;
     using X = MomentExchange<R, NA, LM, S>;
     constexpr int OWN = X::OWN, TEAMS = kBlock / S;
@@ -588,6 +709,13 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
             const int lm = lane + S * o;
             if (lm < LM) dA_out[((long)i * NA + n) * LM + lm] = acc[n][o];
         }
+    if (NET) {
+        R dq[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) dq[d] = d < NR ? dqR[d] : part[d - NR];
+        team_network_backward<R, D, S>(lane, dm, theta, a, qscale, dq, R(ebar_s[s]), i, e_in, t_in, abar_out,
+                                       alpha_out, beta_out, gamma_out);
+    }
 }
 
 // -------------------------------------------------- angular coefficient grad
@@ -841,7 +969,7 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
              const int64_t* __restrict__ soff, int chunk, const R* __restrict__ q_in, const R* __restrict__ dq_in,
              const R* __restrict__ abar, const R* __restrict__ e_in, const R* __restrict__ alpha,
              const R* __restrict__ beta, const R* __restrict__ gam, const R* __restrict__ S0,
-             const R* __restrict__ S1, double* __restrict__ partial) {
+             const R* __restrict__ S1, int units_by_atom, double* __restrict__ partial) {
     using MM = OuterMma<R>;
     using OT = OuterTiles<R>;
     constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D, SC = OT::SC, MAXTW = OT::MAXTW;
@@ -878,12 +1006,15 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
     for (long s0 = lo; s0 < hi; s0 += SC) {
         const int n = int(hi - s0 < SC ? hi - s0 : SC);
         __syncthreads();
-        // per-unit rows: contiguous in the species-sorted list
+        // per-unit rows: contiguous in the species-sorted list, or (written by
+        // the sweeps) indexed by atom
         for (int x = threadIdx.x; x < SC * H; x += kBlock) {
             const bool in = x < n * H;
-            Xa[x] = in ? alpha[s0 * H + x] : R(0);
-            Xb[x] = in ? beta[s0 * H + x] : R(0);
-            Xg[x] = in ? gam[s0 * H + x] : R(0);
+            long src = s0 * H + x;
+            if (units_by_atom && in) src = long(order[s0 + x / H]) * H + x % H;
+            Xa[x] = in ? alpha[src] : R(0);
+            Xb[x] = in ? beta[src] : R(0);
+            Xg[x] = in ? gam[src] : R(0);
         }
         // per-atom rows, gathered by atom index
         for (int x = threadIdx.x; x < SC * D; x += kBlock) {

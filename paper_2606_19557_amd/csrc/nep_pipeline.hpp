@@ -42,10 +42,19 @@ nep_status run_shape(const Ctx& c) {
     }
 
     R* q = (c.mode == Mode::Descriptors || c.desc_out) && c.desc_out ? static_cast<R*>(c.desc_out) : Wr(L.q);
+    // network 3: each atom's network runs in its team at the end of the
+    // descriptor (forward) and tangent (Hessian-vector product) sweeps
+    const bool fused = c.plan.network == 3 && c.mode != Mode::Descriptors;
     if (Na > 0 && (rs = with_team(c.plan.team_desc, [&](auto S_) -> nep_status {
             constexpr int S = decltype(S_)::value;
-            NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
-                       c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0));
+            if (fused)
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, true>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+                           theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
+                           Wr(L.t));
+            else
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, false>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+                           theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), nullptr, nullptr, nullptr,
+                           nullptr);
             return NEP_OK;
         })))
         return rs;
@@ -56,7 +65,7 @@ nep_status run_shape(const Ctx& c) {
     if (Na > 0 && lane_net)
         NEP_LAUNCH("network_forward", (k_network_forward_lane<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
                    qscale, c.species_order, c.species_offset, q, Wr(L.Eat), Wr(L.e), Wr(L.t));
-    if (Na > 0 && !lane_net)
+    if (Na > 0 && !lane_net && !fused)
         NEP_LAUNCH("network_forward", (k_network_forward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta, qscale,
                    c.species_order, c.species_offset, q, Wr(L.Eat), Wr(L.e), Wr(L.t));
 
@@ -91,13 +100,21 @@ nep_status run_shape(const Ctx& c) {
     if (Na > 0) {
         if ((rs = with_team(c.plan.team_tangent, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
-                NEP_LAUNCH("tangent", (k_tangent<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
-                           c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar), Wr(L.A),
-                           Wr(L.dq), Wr(L.dA), Wr(L.S1));
+                if (fused)
+                    NEP_LAUNCH("tangent", (k_tangent<R, Sh, S, true>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+                               theta, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
+                               Wr(L.A), Wr(L.dq), Wr(L.dA), Wr(L.S1), qscale, Wd(L.ebar), Wr(L.e), Wr(L.t),
+                               Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
+                else
+                    NEP_LAUNCH("tangent", (k_tangent<R, Sh, S, false>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+                               theta, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
+                               Wr(L.A), Wr(L.dq), Wr(L.dA), Wr(L.S1), nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr);
                 return NEP_OK;
             })))
             return rs;
-        if (lane_net)
+        if (fused) {
+        } else if (lane_net)
             NEP_LAUNCH("network_backward", (k_network_backward_lane<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm,
                        theta, qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq),
                        Wr(L.e), Wr(L.t), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
@@ -122,7 +139,7 @@ nep_status run_shape(const Ctx& c) {
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(og_shm)));
         NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), og_shm, st, dm, qscale,
                    c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha),
-                   Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), Wd(L.outer_part));
+                   Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), fused ? 1 : 0, Wd(L.outer_part));
     }
     if (Na > 0 && dm.offB1 > 0)
         NEP_LAUNCH("reduce_stage", k_reduce_stage<kRedBlock / 64>, dim3(int((dm.offB1 + 63) / 64), kStageGroups), dim3(kRedBlock), 0,

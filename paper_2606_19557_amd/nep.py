@@ -130,7 +130,7 @@ class Plan:
     team_coeff_grad: int = 0
     coeff_grad_blocks: int = 0
     outer_chunk: int = 0
-    network: int = 0  # 1 = matrix-core tiles, 2 = one lane per atom
+    network: int = 0  # 1 = matrix-core tiles, 2 = one lane per atom, 3 = inside the sweeps
 
     def c(self) -> c_plan:
         return c_plan(self.team_descriptor, self.team_force, self.team_tangent, self.team_coeff_grad,

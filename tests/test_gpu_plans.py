@@ -19,6 +19,8 @@ PLANS = [
     N.Plan(4, 16, 8, 16, 1, 8, 1),
     N.Plan(16, 4, 16, 8, 7, 100, 2),
     N.Plan(8, 8, 8, 32, 300, 64, 1),
+    N.Plan(4, 8, 16, 8, 2048, 64, 3),
+    N.Plan(16, 8, 4, 16, 64, 16, 3),
 ]
 
 
@@ -70,7 +72,7 @@ def test_autotune_returns_valid_plan():
         assert getattr(plan, k) in (4, 8, 16)
     assert plan.team_coeff_grad in (4, 8, 16, 32)
     assert plan.coeff_grad_blocks in (512, 1024, 2048, 4096) and plan.outer_chunk in (32, 64, 128, 256)
-    assert plan.network in (1, 2)
+    assert plan.network in (1, 2, 3)
     tuned = model.with_plan(plan)
     l0, g0 = N.nep_loss_and_grad(model, theta, qs, gb, nb, targets)
     l1, g1 = N.nep_loss_and_grad(tuned, theta, qs, gb, nb, targets)
