@@ -951,7 +951,13 @@ struct OuterMma : Mfma<R> {
 template <typename R>
 struct OuterTiles {
     static constexpr int SC = sizeof(R) == 4 ? 32 : 16;  // atoms per staged sub-chunk
-    static constexpr int MAXTW = 6;                        // tiles per wave
+    static constexpr int MAXTW = 6;                        // tiles per wave at most
+    // accumulator slots the kernel is built with for a network: the smallest
+    // of 1, 2, 4, 6 covering its tiles (fewer slots, fewer registers)
+    __host__ __device__ static int tiles_per_wave(const Dims& d) {
+        const int t = (tiles(d) + WAVES - 1) / WAVES;
+        return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 6;
+    }
     static constexpr int WAVES = kBlock / 64;
     __host__ __device__ static int floats_per_atom(const Dims& d) {
         return 3 * d.H + 2 * d.D + 2 * d.NR + 2 * d.T * d.KR;
@@ -963,7 +969,7 @@ struct OuterTiles {
     }
 };
 
-template <typename R, class Sh>
+template <typename R, class Sh, int MAXTW>
 __global__ void __launch_bounds__(kBlock)
 k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict__ order,
              const int64_t* __restrict__ soff, int chunk, const R* __restrict__ q_in, const R* __restrict__ dq_in,
@@ -972,7 +978,7 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
              const R* __restrict__ S1, int units_by_atom, double* __restrict__ partial) {
     using MM = OuterMma<R>;
     using OT = OuterTiles<R>;
-    constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D, SC = OT::SC, MAXTW = OT::MAXTW;
+    constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D, SC = OT::SC;
     constexpr int WAVES = OT::WAVES, KSTEPS = 2 * SC / MM::KPI;
     extern __shared__ __align__(16) unsigned char outer_smem[];
     const int T = dm.T, H = dm.H, TK = T * KR;
@@ -1002,42 +1008,109 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
     for (int k = 0; k < MAXTW; ++k)
 #pragma unroll
         for (int v = 0; v < MM::NV; ++v) acc[k][v] = R(0);
+    // atom index of each sub-chunk slot, double-buffered: the next
+    // sub-chunk's indices load during the current staging. Slots
+    // past the chunk hold 0, a valid atom, so every staging load below is
+    // unconditional (its value is then replaced by zero).
+    __shared__ int ord[2][SC];
+    if (threadIdx.x < SC) ord[0][threadIdx.x] = lo + threadIdx.x < hi ? order[lo + threadIdx.x] : 0;
+    int buf = 0;
+    constexpr int U = 4;  // staging iterations whose loads are issued together
     R sa = R(0), sg = R(0);  // b0 / w1 column sums of unit mu = threadIdx.x (H <= kBlock)
-    for (long s0 = lo; s0 < hi; s0 += SC) {
+    for (long s0 = lo; s0 < hi; s0 += SC, buf ^= 1) {
         const int n = int(hi - s0 < SC ? hi - s0 : SC);
+        const int* os = ord[buf];
         __syncthreads();
+        // the next sub-chunk's atom indices, issued before this one's staging
+        int nxt = 0;
+        if (threadIdx.x < SC && s0 + SC + threadIdx.x < hi) nxt = order[s0 + SC + threadIdx.x];
         // per-unit rows: contiguous in the species-sorted list, or (written by
         // the sweeps) indexed by atom
-        for (int x = threadIdx.x; x < SC * H; x += kBlock) {
-            const bool in = x < n * H;
-            long src = s0 * H + x;
-            if (units_by_atom && in) src = long(order[s0 + x / H]) * H + x % H;
-            Xa[x] = in ? alpha[src] : R(0);
-            Xb[x] = in ? beta[src] : R(0);
-            Xg[x] = in ? gam[src] : R(0);
+        for (int x0 = threadIdx.x; x0 < SC * H; x0 += U * kBlock) {
+            R va[U], vb[U], vg[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                const bool in = x < n * H;
+                const int sl = in ? x / H : 0, c = in ? x % H : 0;
+                const long src = units_by_atom ? long(os[sl]) * H + c : (s0 + sl) * H + c;
+                va[u] = alpha[src];
+                vb[u] = beta[src];
+                vg[u] = gam[src];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                if (x >= SC * H) continue;
+                const bool in = x < n * H;
+                Xa[x] = in ? va[u] : R(0);
+                Xb[x] = in ? vb[u] : R(0);
+                Xg[x] = in ? vg[u] : R(0);
+            }
         }
         // per-atom rows, gathered by atom index
-        for (int x = threadIdx.x; x < SC * D; x += kBlock) {
-            const int sl = x / D, v = x % D;
-            const bool in = sl < n;
-            const long i = in ? long(order[s0 + sl]) : 0;
-            Yq[x] = in ? qscale[v] * q_in[i * D + v] : R(0);
-            Yd[x] = in ? qscale[v] * dq_in[i * D + v] : R(0);
+        for (int x0 = threadIdx.x; x0 < SC * D; x0 += U * kBlock) {
+            R vq[U], vd[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                const bool in = x < n * D;
+                const int v = in ? x % D : 0;
+                const long i = os[in ? x / D : 0];
+                const R sv = qscale[v];
+                vq[u] = sv * q_in[i * D + v];
+                vd[u] = sv * dq_in[i * D + v];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                if (x >= SC * D) continue;
+                const bool in = x < n * D;
+                Yq[x] = in ? vq[u] : R(0);
+                Yd[x] = in ? vd[u] : R(0);
+            }
         }
-        for (int x = threadIdx.x; x < SC * NR; x += kBlock) {
-            const int sl = x / NR, r = x % NR;
-            const bool in = sl < n;
-            const long i = in ? long(order[s0 + sl]) : 0;
-            Ra[x] = in ? abar[i * D + r] : R(0);
-            Re[x] = in ? e_in[i * D + r] : R(0);
+        for (int x0 = threadIdx.x; x0 < SC * NR; x0 += U * kBlock) {
+            R va[U], ve[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                const bool in = x < n * NR;
+                const int r = in ? x % NR : 0;
+                const long i = os[in ? x / NR : 0];
+                va[u] = abar[i * D + r];
+                ve[u] = e_in[i * D + r];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                if (x >= SC * NR) continue;
+                const bool in = x < n * NR;
+                Ra[x] = in ? va[u] : R(0);
+                Re[x] = in ? ve[u] : R(0);
+            }
         }
-        for (int x = threadIdx.x; x < SC * TK; x += kBlock) {
-            const int sl = x / TK, c = x % TK;
-            const bool in = sl < n;
-            const long i = in ? long(order[s0 + sl]) : 0;
-            C0[x] = in ? S0[i * TK + c] : R(0);
-            C1[x] = in ? S1[i * TK + c] : R(0);
+        for (int x0 = threadIdx.x; x0 < SC * TK; x0 += U * kBlock) {
+            R v0[U], v1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                const bool in = x < n * TK;
+                const int c = in ? x % TK : 0;
+                const long i = os[in ? x / TK : 0];
+                v0[u] = S0[i * TK + c];
+                v1[u] = S1[i * TK + c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = x0 + u * kBlock;
+                if (x >= SC * TK) continue;
+                const bool in = x < n * TK;
+                C0[x] = in ? v0[u] : R(0);
+                C1[x] = in ? v1[u] : R(0);
+            }
         }
+        if (threadIdx.x < SC) ord[buf ^ 1][threadIdx.x] = nxt;
         __syncthreads();
         if (threadIdx.x < H)
             for (int sl = 0; sl < n; ++sl) {

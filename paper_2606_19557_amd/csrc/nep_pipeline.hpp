@@ -134,12 +134,23 @@ nep_status run_shape(const Ctx& c) {
             })))
             return rs;
         const size_t og_shm = OuterTiles<R>::lds_bytes(dm);
-        if (og_shm > 64 * 1024)
-            NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_outer_grad<R, Sh>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(og_shm)));
-        NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh>), dim3(L.outer_rows), dim3(kBlock), og_shm, st, dm, qscale,
-                   c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e), Wr(L.alpha),
-                   Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), fused ? 1 : 0, Wd(L.outer_part));
+        auto outer = [&](auto TW_) -> nep_status {
+            constexpr int TW = decltype(TW_)::value;
+            if (og_shm > 64 * 1024)
+                NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_outer_grad<R, Sh, TW>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(og_shm)));
+            NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh, TW>), dim3(L.outer_rows), dim3(kBlock), og_shm, st, dm,
+                       qscale, c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e),
+                       Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), fused ? 1 : 0, Wd(L.outer_part));
+            return NEP_OK;
+        };
+        switch (OuterTiles<R>::tiles_per_wave(dm)) {
+            case 1: rs = outer(std::integral_constant<int, 1>{}); break;
+            case 2: rs = outer(std::integral_constant<int, 2>{}); break;
+            case 4: rs = outer(std::integral_constant<int, 4>{}); break;
+            default: rs = outer(std::integral_constant<int, 6>{}); break;
+        }
+        if (rs) return rs;
     }
     if (Na > 0 && dm.offB1 > 0)
         NEP_LAUNCH("reduce_stage", k_reduce_stage<kRedBlock / 64>, dim3(int((dm.offB1 + 63) / 64), kStageGroups), dim3(kRedBlock), 0,
