@@ -52,6 +52,7 @@ def parse():
                    help="oracle threads for the CPU baseline (default: the host's cores, at most 16)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="repeat the oracle over the sample until this much time has passed")
+    p.add_argument("--json-out", default=None, help="also write the result line to this file")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also run one device-to-device copy of this many MiB (a known-size kernel that "
                         "calibrates hardware byte counters)")
@@ -81,8 +82,16 @@ def basis_flops(K, deriv):
     return 13 + K * (12 if deriv else 4)
 
 
-def work_model(name, md, n):
-    """(flops, bytes) of one launch of kernel `name`; n holds the batch counts."""
+def work_model(name, md, n, fused=False):
+    """(flops, bytes) of one launch of kernel `name`; n holds the batch counts.
+    `fused`: the network runs inside the descriptor and tangent sweeps (plan
+    network 3), which then also do the network passes' work."""
+    if fused and name in ("descriptor", "tangent"):
+        fl, by = work_model(name, md, n)
+        nf, nb = work_model("network_forward" if name == "descriptor" else "network_backward", md, n)
+        D = md["n_max_r"] + 1 + (md["n_max_a"] + 1) * (md["l_max"] + (md["l_max_4b"] == 2) + (md["l_max_5b"] == 1))
+        # the descriptor (or its tangent) is in registers: not read again
+        return fl + nf, by + nb - n["atoms"] * (4 + n["real_bytes"] * D)
     KR, KA = md["basis_r"] + 1, md["basis_a"] + 1
     NR, NA = md["n_max_r"] + 1, md["n_max_a"] + 1
     T, H, L = md["num_types"], md["hidden"], md["l_max"]
@@ -145,14 +154,19 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, plan=None):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none or the sources changed since it was taken."""
+    None when there is none, the sources changed since it was taken, or it was
+    taken under another launch plan than `plan` (a dict of plan fields)."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
     if not os.path.exists(path):
         return None
     digest, val = None, None
     for line in open(path):
+        if line.startswith("plan:") and plan is not None:
+            taken = json.loads(line.split(":", 1)[1])
+            if any(taken.get(k) != v for k, v in plan.items()):
+                return None
         if line.startswith("source-sha256:"):
             digest = line.split(":", 1)[1].strip()
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
@@ -224,7 +238,7 @@ def main():
             f"{sizes[:, 1].mean():.0f} pairs")
     else:
         tune_b, tune_nb, tune_tg = gb, nb, targets
-    plan, plan_cached = None, False
+    plan, plan_cached, plan_key = None, False, None
     if not args.no_autotune:
         from paper_2606_19557_amd import tuning
 
@@ -232,8 +246,10 @@ def main():
         if args.retune:
             plan = N.nep_autotune(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3)
         else:
-            plan, plan_cached = tuning.tuned_plan(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3)
+            plan, plan_cached = tuning.tuned_plan(model, theta, qs, tune_b, tune_nb, tune_tg, repeats=3,
+                                                  shipped=tuning.SHIPPED_PLANS)
         model = model.with_plan(plan)
+        plan_key = tuning.plan_key(model, tune_b.num_atoms, tune_nb.num_pairs)
         log(f"{'cached' if plan_cached else 'autotuned'} plan in {time.perf_counter() - t0:.2f} s: {plan.as_dict()}")
     if epoch_mode:
         data.model = model
@@ -306,14 +322,17 @@ def main():
         log(f"  kernel {name:22s} launches {n:4d}  avg {tot / n * 1e3:9.2f} us")
     dom = max(rows, key=lambda r: r[2] * (r[1] / args.profile_steps))
     name, n, avg_ms = dom
-    work = work_model(name, w.model, counts)
+    used_plan = plan.as_dict() if plan is not None else dict(
+        team_descriptor=8, team_force=8, team_tangent=8, team_coeff_grad=8, coeff_grad_blocks=2048, outer_chunk=64,
+        network=1)
+    work = work_model(name, w.model, counts, fused=used_plan["network"] == 3)
     peak_alu = PEAK_FP64_TFLOPS if w.dtype == "f64" else PEAK_FP32_TFLOPS
     roof = None
     if work is not None:
         fl, by = work
         sec = avg_ms * 1e-3
         t_alu, t_hbm = fl / (peak_alu * 1e12), by / (PEAK_HBM_GBS * 1e9)
-        traffic = measured_traffic(name, args.workload)
+        traffic = measured_traffic(name, args.workload, used_plan)
         if t_alu >= t_hbm:
             achieved, peak = fl / sec / 1e12, peak_alu
             roof = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
@@ -406,7 +425,7 @@ def main():
         "config": {"workload": f"{args.workload}: {w.description}",
                    "structures": host.num_structures, "atoms": host.num_atoms, "pairs": nb.num_pairs,
                    "angular_pairs": nb.num_angular_pairs, "parallelism": "single GPU",
-                   "plan": None if plan is None else dict(plan.as_dict(), from_cache=plan_cached),
+                   "plan": None if plan is None else dict(plan.as_dict(), from_cache=plan_cached, key=plan_key),
                    **({"minibatch": w.minibatch, "steps_per_epoch": len(mbs),
                        "epoch_s": round(ms * len(mbs) * 1e-3, 5)} if epoch_mode else {})},
         "roofline": roof,
@@ -416,6 +435,9 @@ def main():
         "neighbor_build_ms": round(nbr_ms, 2),
     }
     print(json.dumps(out), flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(json.dumps(out) + "\n")
 
 
 if __name__ == "__main__":

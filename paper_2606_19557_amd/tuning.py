@@ -4,7 +4,9 @@ A plan depends on the model shape and precision and on the batch's size and
 neighbour density, so the key holds those (atoms and pairs per atom in
 power-of-two buckets): a new batch of the same kind reuses the plan without
 timing again. The cache is a plain JSON object {key: plan fields}; its path is
-$NEP_PLAN_CACHE, else ~/.cache/nep_mi355x/plans.json.
+$NEP_PLAN_CACHE, else ~/.cache/nep_mi355x/plans.json. `plans_mi355x.json`
+beside this module holds plans the autotuner chose on an MI355X for the
+benchmark workloads; callers may pass it as a read-only fallback.
 """
 
 from __future__ import annotations
@@ -17,6 +19,7 @@ import tempfile
 from .nep import Batch, Model, Neighbors, Plan, Targets, nep_autotune
 
 _FIELDS = tuple(Plan.__dataclass_fields__)
+SHIPPED_PLANS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans_mi355x.json")
 
 
 def cache_path() -> str:
@@ -54,15 +57,24 @@ def store(entries: dict, path: str | None = None):
     os.replace(tmp, path)
 
 
-def tuned_plan(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, targets: Targets, repeats: int = 3,
-               path: str | None = None, tuner=nep_autotune) -> tuple[Plan, bool]:
-    """(plan, from_cache): the cached plan for this kind of batch, or a freshly
-    tuned one (then stored)."""
-    key = plan_key(model, batch.num_atoms, nbr.num_pairs)
-    entries = load(path)
+def _entry(entries: dict, key: str) -> Plan | None:
     hit = entries.get(key)
     if isinstance(hit, dict) and set(hit) >= set(_FIELDS):
-        return Plan(**{k: int(hit[k]) for k in _FIELDS}), True
+        return Plan(**{k: int(hit[k]) for k in _FIELDS})
+    return None
+
+
+def tuned_plan(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, targets: Targets, repeats: int = 3,
+               path: str | None = None, tuner=nep_autotune, shipped: str | None = None) -> tuple[Plan, bool]:
+    """(plan, from_cache): the cached plan for this kind of batch, else the one
+    in the read-only `shipped` file, else a freshly tuned one (then stored)."""
+    key = plan_key(model, batch.num_atoms, nbr.num_pairs)
+    entries = load(path)
+    plan = _entry(entries, key)
+    if plan is None and shipped:
+        plan = _entry(load(shipped), key)
+    if plan is not None:
+        return plan, True
     plan = tuner(model, theta, q_scale, batch, nbr, targets, repeats=repeats)
     entries[key] = plan.as_dict()
     store(entries, path)

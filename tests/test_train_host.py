@@ -84,3 +84,14 @@ def test_plan_cache_roundtrip(tmp_path):
     _, cached3 = tuning.tuned_plan(m, None, None, b3, n3, None, path=path, tuner=fake_tuner)
     assert not cached3 and len(calls) == 2
     assert len(tuning.load(path)) == 2
+    # a read-only shipped file answers misses of the user cache, which wins on a hit
+    shipped = str(tmp_path / "shipped.json")
+    b4, n4 = SimpleNamespace(num_atoms=300000), SimpleNamespace(num_pairs=300000 * 100)
+    key4 = tuning.plan_key(m, b4.num_atoms, n4.num_pairs)
+    tuning.store({key4: nep.Plan(16, 16, 16, 32, 512, 256, 3).as_dict(),
+                  tuning.plan_key(m, b1.num_atoms, n1.num_pairs): nep.Plan(8, 8, 8, 8, 64, 64, 1).as_dict()}, shipped)
+    p4, cached4 = tuning.tuned_plan(m, None, None, b4, n4, None, path=path, tuner=fake_tuner, shipped=shipped)
+    assert cached4 and p4 == nep.Plan(16, 16, 16, 32, 512, 256, 3) and len(calls) == 2
+    p5, _ = tuning.tuned_plan(m, None, None, b1, n1, None, path=path, tuner=fake_tuner, shipped=shipped)
+    assert p5 == p
+    assert len(tuning.load(path)) == 2  # shipped plans are not copied into the user cache
