@@ -313,10 +313,40 @@ __device__ __forceinline__ void q4_hess_vec(const R* a, const R* da, R* out) {
 // ------------------------------------------------------------ team reduce
 
 // Sum over the S consecutive lanes of a team (S a power of two <= 64).
+// Lane permutes of the DPP modifier (encodings of the dpp_ctrl field):
+// exchange with lane ^ 1 and lane ^ 2 inside each quad, and the mirror of the
+// lane inside its half row (8 lanes) and its row (16 lanes).
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i in each group of 8
+constexpr int kDppMirror = 0x140;      // lane i <- lane 15 - i in each row of 16
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_read(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+
+// Sum over the S consecutive lanes of a team (S a power of two <= 32), every
+// lane getting the same bits: a butterfly whose partner reads are DPP lane
+// permutes inside the add (xor 1, xor 2, then the half-row and row mirrors,
+// which pair each group with the other half of its next-larger group); only
+// the step across 16 lanes of a 32-lane team goes through a cross-lane
+// shuffle. Each step adds two equal-rank partial sums, so partners agree.
 template <int S, typename R>
 __device__ __forceinline__ R team_sum(R v) {
-#pragma unroll
-    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16 || S == 32, "team size");
+    if (S >= 2) v += dpp_read<kDppXor1>(v);
+    if (S >= 4) v += dpp_read<kDppXor2>(v);
+    if (S >= 8) v += dpp_read<kDppHalfMirror>(v);
+    if (S >= 16) v += dpp_read<kDppMirror>(v);
+    if (S >= 32) v += __shfl_xor(v, 16, 64);
     return v;
 }
 
