@@ -93,43 +93,66 @@ __device__ __forceinline__ void team_network_forward(int lane, const Dims& dm, c
         if (v % S == lane) e_out[i * D + v] = qscale[v] * ev[v];
 }
 
+// Loads of the first step of team_network_backward (units mu = lane and
+// lane + S, their weight rows, activations, the atom's e entries and ebar),
+// issued by the caller ahead of other work so their latency overlaps it.
+template <typename R, int D, int S>
+struct NetBackFirst {
+    static constexpr int OWNV = (D + S - 1) / S;
+    R w[D], w2[D], t, t2, wm, wm2, eo[OWNV], eb;
+    bool two;
+    __device__ __forceinline__ void load(int lane, const Dims& dm, const R* __restrict__ theta, int a,
+                                         const R* __restrict__ t_in, const R* __restrict__ e_in,
+                                         const double* __restrict__ ebar_s, int s, long i) {
+        const int H = dm.H;
+        const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
+        const R* __restrict__ w1 = W0 + (long)H * D + H;
+        const int mu = lane < H ? lane : 0;  // lanes past H run one discarded step
+        two = lane + S < H;
+        const int mu2 = two ? lane + S : mu;
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            w[v] = W0[(long)mu * D + v];
+            w2[v] = W0[(long)mu2 * D + v];
+        }
+        t = t_in[i * H + mu];
+        t2 = t_in[i * H + mu2];
+        wm = lane < H ? w1[mu] : R(0);
+        wm2 = two ? w1[mu2] : R(0);
+#pragma unroll
+        for (int o = 0; o < OWNV; ++o) eo[o] = lane + S * o < D ? e_in[i * D + lane + S * o] : R(0);
+        eb = R(ebar_s[s]);
+    }
+};
+
 // The Hessian-vector product and weight-gradient factors of the force/virial
 // adjoint for one atom (as the network backward pass): da = W0 (s dq),
 // alpha = w1 s'(ebar - 2 t da), beta = w1 s', gamma = ebar t + s' da,
-// abar = ebar e + s (W0^T (-2 w1 t s' da)); every lane holds dq.
+// abar = ebar e + s (W0^T (-2 w1 t s' da)); every lane holds dq. Two hidden
+// units per step (mu and mu + S); the first step's operands come in `f`.
 template <typename R, int D, int S>
 __device__ __forceinline__ void team_network_backward(int lane, const Dims& dm, const R* __restrict__ theta, int a,
-                                                      const R* __restrict__ qscale, const R (&dq)[D], R eb, long i,
-                                                      const R* __restrict__ e_in, const R* __restrict__ t_in,
+                                                      const R* __restrict__ qscale, const R (&dq)[D], long i,
+                                                      const NetBackFirst<R, D, S>& f, const R* __restrict__ t_in,
                                                       R* __restrict__ abar_out, R* __restrict__ alpha_out,
                                                       R* __restrict__ beta_out, R* __restrict__ gamma_out) {
     const int H = dm.H;
     const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
     const R* __restrict__ w1 = W0 + (long)H * D + H;
+    const R eb = f.eb;
     R dk[D], z[D];
 #pragma unroll
     for (int v = 0; v < D; ++v) {
         dk[v] = qscale[v] * dq[v];
         z[v] = R(0);
     }
-    // the atom's e entries this lane writes abar for, loaded up front
-    constexpr int OWNV = (D + S - 1) / S;
-    R eo[OWNV];
-#pragma unroll
-    for (int o = 0; o < OWNV; ++o) eo[o] = lane + S * o < D ? e_in[i * D + lane + S * o] : R(0);
-    // two hidden units per step, as in the forward pass
-    for (int mu = lane; mu < H; mu += 2 * S) {
-        const bool two = mu + S < H;
-        const int mu2 = two ? mu + S : mu;
-        const R* __restrict__ w = W0 + (long)mu * D;
-        const R* __restrict__ w2 = W0 + (long)mu2 * D;
-        const R t = t_in[i * H + mu], t2 = t_in[i * H + mu2];
-        const R wm = w1[mu], wm2 = two ? w1[mu2] : R(0);
+    // one step: units mu (and mu2 when `two`), rows read through wr / wr2
+    auto step = [&](int mu, int mu2, bool two, R t, R t2, R wm, R wm2, auto wr, auto wr2) {
         R da = R(0), da2 = R(0);
 #pragma unroll
         for (int v = 0; v < D; ++v) {
-            da += w[v] * dk[v];
-            da2 += w2[v] * dk[v];
+            da += wr(v) * dk[v];
+            da2 += wr2(v) * dk[v];
         }
         const R sp = R(1) - t * t, sp2 = R(1) - t2 * t2;
         alpha_out[i * H + mu] = wm * sp * (eb - R(2) * t * da);
@@ -142,13 +165,24 @@ __device__ __forceinline__ void team_network_backward(int lane, const Dims& dm, 
         }
         const R c = R(-2) * wm * t * sp * da, c2 = R(-2) * wm2 * t2 * sp2 * da2;
 #pragma unroll
-        for (int v = 0; v < D; ++v) z[v] += w[v] * c + w2[v] * c2;
+        for (int v = 0; v < D; ++v) z[v] += wr(v) * c + wr2(v) * c2;
+    };
+    if (lane < H)
+        step(lane, f.two ? lane + S : lane, f.two, f.t, f.t2, f.wm, f.wm2, [&](int v) { return f.w[v]; },
+             [&](int v) { return f.w2[v]; });
+    for (int mu = lane + 2 * S; mu < H; mu += 2 * S) {
+        const bool two = mu + S < H;
+        const int mu2 = two ? mu + S : mu;
+        const R* __restrict__ w = W0 + (long)mu * D;
+        const R* __restrict__ w2 = W0 + (long)mu2 * D;
+        step(mu, mu2, two, t_in[i * H + mu], t_in[i * H + mu2], w1[mu], two ? w1[mu2] : R(0),
+             [&](int v) { return w[v]; }, [&](int v) { return w2[v]; });
     }
 #pragma unroll
     for (int v = 0; v < D; ++v) z[v] = team_sum<S>(z[v]);
 #pragma unroll
     for (int v = 0; v < D; ++v)
-        if (v % S == lane) abar_out[i * D + v] = eb * eo[v / S] + qscale[v] * z[v];
+        if (v % S == lane) abar_out[i * D + v] = eb * f.eo[v / S] + qscale[v] * z[v];
 }
 
 // ------------------------------------------------------------------ descriptor
@@ -649,6 +683,10 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
                 if (kk % S == lane) S1_out[((long)i * T + b) * KR + kk] = Sb[kk];
         }
     }
+    // the network step's first operands load while the invariant tangents
+    // below wait for the moments
+    NetBackFirst<R, D, S> nf;
+    if (NET && live) nf.load(lane, dm, theta, a, t_in, e_in, ebar_s, s, i);
     // invariant tangents: contractions with the atom's own moments A, split
     // over the owned harmonics and summed over the team
     R part[DANG];
@@ -713,8 +751,8 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
         R dq[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) dq[d] = d < NR ? dqR[d] : part[d - NR];
-        team_network_backward<R, D, S>(lane, dm, theta, a, qscale, dq, R(ebar_s[s]), i, e_in, t_in, abar_out,
-                                       alpha_out, beta_out, gamma_out);
+        team_network_backward<R, D, S>(lane, dm, theta, a, qscale, dq, i, nf, t_in, abar_out, alpha_out, beta_out,
+                                       gamma_out);
     }
 }
 
