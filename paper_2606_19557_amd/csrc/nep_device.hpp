@@ -313,6 +313,17 @@ __device__ __forceinline__ void q4_hess_vec(const R* a, const R* da, R* out) {
 // ------------------------------------------------------------ team reduce
 
 // Sum over the S consecutive lanes of a team (S a power of two <= 64).
+// Workgroups are dispatched to the 8 XCDs round-robin by block index, each
+// XCD with its own L2. xcd_tile maps block b of an nb-block grid to a tile so
+// that every XCD walks one contiguous range of tiles (a bijection on
+// [0, nb)): neighbouring atoms, and the pair slots they write for each other,
+// then share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int per = nb / kXcds, rem = nb % kXcds, x = b % kXcds, k = b / kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // Lane permutes of the DPP modifier (encodings of the dpp_ctrl field):
 // exchange with lane ^ 1 and lane ^ 2 inside each quad, and the mirror of the
 // lane inside its half row (8 lanes) and its row (16 lanes).

@@ -205,7 +205,7 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
     __shared__ R xbuf[TEAMS * X::TEAM_FLOATS];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     R* tbuf = xbuf + team * X::TEAM_FLOATS;
-    const int i = blockIdx.x * TEAMS + team;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
@@ -402,7 +402,7 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
     constexpr int TEAMS = kBlock / S;
     __shared__ R Bsh[TEAMS][NA * LM];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = blockIdx.x * TEAMS + team;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(kBlock)
 k_force_gather(int Na, const int64_t* __restrict__ row, const Rec<R>* __restrict__ h_in,
                const R* __restrict__ Fown, R* __restrict__ F_out) {
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = blockIdx.x * (kBlock / S) + team;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * (kBlock / S) + team;
     const bool live = i < Na;
     const int64_t p0 = live ? row[i] : 0, p1 = live ? row[i + 1] : 0;
     R f[3] = {R(0), R(0), R(0)};
@@ -578,7 +578,7 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
     __shared__ R xbuf[TEAMS * X::TEAM_FLOATS];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     R* tbuf = xbuf + team * X::TEAM_FLOATS;
-    const int i = blockIdx.x * TEAMS + team;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
