@@ -85,13 +85,23 @@ def basis_flops(K, deriv):
 def work_model(name, md, n, fused=False):
     """(flops, bytes) of one launch of kernel `name`; n holds the batch counts.
     `fused`: the network runs inside the descriptor and tangent sweeps (plan
-    network 3), which then also do the network passes' work."""
+    network 3), which then also do the network passes' work, and the
+    descriptor sweep the force pass's."""
     if fused and name in ("descriptor", "tangent"):
         fl, by = work_model(name, md, n)
         nf, nb = work_model("network_forward" if name == "descriptor" else "network_backward", md, n)
         D = md["n_max_r"] + 1 + (md["n_max_a"] + 1) * (md["l_max"] + (md["l_max_4b"] == 2) + (md["l_max_5b"] == 1))
         # the descriptor (or its tangent) is in registers: not read again
-        return fl + nf, by + nb - n["atoms"] * (4 + n["real_bytes"] * D)
+        fl, by = fl + nf, by + nb - n["atoms"] * (4 + n["real_bytes"] * D)
+        if name == "descriptor":
+            ff, fb = work_model("force", md, n)
+            LM = (md["l_max"] + 1) ** 2 - 1
+            NA, r = md["n_max_a"] + 1, n["real_bytes"]
+            # records, moments, e and the per-atom indices were read or made
+            # by the same kernel
+            fb -= 4 * r * n["pairs"] + n["atoms"] * (8 + 4 + 4 + 8 * md["num_types"] + r * (NA * LM + D))
+            fl, by = fl + ff, by + fb
+        return fl, by
     KR, KA = md["basis_r"] + 1, md["basis_a"] + 1
     NR, NA = md["n_max_r"] + 1, md["n_max_a"] + 1
     T, H, L = md["num_types"], md["hidden"], md["l_max"]

@@ -608,9 +608,10 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
                 g_prof_on = was_on;
                 return s;
             }
-            // the fused network (3) adds to the descriptor and tangent sweeps
+            // the fused network (3) adds to the descriptor and tangent sweeps,
+            // and the descriptor sweep then also runs the force pass
             const double t = get(avg, "network_forward") + get(avg, "network_backward") + get(avg, "descriptor") +
-                             get(avg, "tangent") + get(avg, "outer_grad");
+                             get(avg, "tangent") + get(avg, "outer_grad") + get(avg, "force");
             if (t < tb) {
                 tb = t;
                 keep = p;

@@ -185,6 +185,27 @@ __device__ __forceinline__ void team_network_backward(int lane, const Dims& dm, 
         if (v % S == lane) abar_out[i * D + v] = eb * f.eo[v / S] + qscale[v] * z[v];
 }
 
+// defined further down, used by the descriptor sweep when it also runs the
+// force pass
+template <typename R, class Sh, int S, bool WITH_BP>
+__device__ __forceinline__ void moment_adjoints(int lane, const R* __restrict__ A, const R* __restrict__ dA,
+                                                const R* __restrict__ e, const R* __restrict__ ab, R* B, R* Bp);
+template <typename R, class Sh, int S>
+__device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __restrict__ theta, int i, bool live,
+                                           int a, const int64_t* __restrict__ row, const int* __restrict__ seg,
+                                           const Rec<R>* __restrict__ pairs, const int* __restrict__ reverse,
+                                           const R* Bk, const R* __restrict__ ei, Rec<R>* __restrict__ h_in,
+                                           R* __restrict__ Fown_out, R* __restrict__ Wat_out);
+
+// LDS per team of the descriptor sweep: the moment exchange, grown when the
+// sweep also runs the force pass (the team's B = dE/dA, N_A x 24 values)
+// by whole 128-byte steps, so team blocks keep the exchange's bank pattern.
+template <typename R, int NA, int LM, int S, int FUSE>
+struct DescTeamLds {
+    static constexpr int TF = MomentExchange<R, NA, LM, S>::TEAM_FLOATS, STEP = 128 / int(sizeof(R));
+    static constexpr int floats = (FUSE < 2 || TF >= NA * LM) ? TF : TF + (NA * LM - TF + STEP - 1) / STEP * STEP;
+};
+
 // ------------------------------------------------------------------ descriptor
 
 // q (radial, Eqs. 15-16; angular invariants, Eqs. 19-20 and the 4/5-body
@@ -192,19 +213,21 @@ __device__ __forceinline__ void team_network_backward(int lane, const Dims& dm, 
 // radial basis sums S0[b][k] = sum_{j in b} f_k(r_ij) used by the gradient.
 // Angular pairs are processed S at a time by the team and their (g_n, Y_lm)
 // exchanged through LDS; each lane owns the moments lm = lane + S*o.
-// With NET the team then evaluates the atom's network (E_i, e_i, t_i).
-template <typename R, class Sh, int S, bool NET>
+// FUSE >= 1: the team then evaluates the atom's network (E_i, e_i, t_i);
+// FUSE == 2: and runs the atom's force pass (h, own-direction F, virial).
+template <typename R, class Sh, int S, int FUSE>
 __global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::descriptor))
 k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
              const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
              R* __restrict__ q_out, R* __restrict__ A_out, R* __restrict__ S0_out, const R* __restrict__ qscale,
-             R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out) {
+             R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out, const int* __restrict__ reverse,
+             Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
     constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D, L = Sh::L;
     using X = MomentExchange<R, NA, LM, S>;
-    constexpr int OWN = X::OWN, TEAMS = kBlock / S;
-    __shared__ R xbuf[TEAMS * X::TEAM_FLOATS];
+    constexpr int OWN = X::OWN, TEAMS = kBlock / S, XR = DescTeamLds<R, NA, LM, S, FUSE>::floats;
+    __shared__ R xbuf[TEAMS * XR];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    R* tbuf = xbuf + team * X::TEAM_FLOATS;
+    R* tbuf = xbuf + team * XR;
     const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
     const bool live = i < Na;
     const int T = dm.T;
@@ -325,7 +348,18 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
             const int lm = lane + S * o;
             if (lm < LM) A_out[((long)i * NA + n) * LM + lm] = acc[n][o];
         }
-    if (NET) team_network_forward<R, D, S>(lane, dm, theta, a, qscale, qv, i, E_out, e_out, t_out);
+    if (FUSE >= 1) team_network_forward<R, D, S>(lane, dm, theta, a, qscale, qv, i, E_out, e_out, t_out);
+    if (FUSE == 2) {
+        // B from the team's just-stored A and e rows (a workgroup-scope fence
+        // makes each lane's stores visible to the other lanes), into the
+        // team's LDS block, whose exchange use has ended
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        moment_adjoints<R, Sh, S, false>(lane, A_out + (long)i * NA * LM, nullptr, e_out + (long)i * D, nullptr,
+                                         tbuf, nullptr);
+        X::wave_fence();
+        force_pass<R, Sh, S>(lane, dm, theta, i, true, a, row, seg, pairs, reverse, tbuf, e_out + (long)i * D, h_in,
+                             Fown_out, Wat_out);
+    }
 }
 
 // ------------------------------------------------ per-atom moment adjoints
@@ -386,36 +420,23 @@ __device__ __forceinline__ void moment_adjoints(int lane, const R* __restrict__ 
 
 // ------------------------------------------------------------------- force
 
-// h_ij = dE_i/dr_ij for every pair of atom i's row, from atom i's own
-// B = dE_i/dA and eps = radial force coefficients only (one direction per
-// pair): the atom's own-direction sum sum_j h_ij, its virial
-// -sum_j r_ij (x) h_ij, and -h_ij written into the slot of the reverse pair
-// (j, i), so that k_force_gather completes F_j = sum h_jk + sum (-h_kj) with
-// contiguous reads and no atomics.
+// The force pass of one atom's team: for every pair of atom i's row,
+// h_ij = dE_i/dr_ij from the atom's own B = dE_i/dA (Bk, the team's LDS copy)
+// and e = dE_i/dq (ei), the radial part through eps_k = sum_n e_n c_R[a][b][n][k]
+// (one direction per pair); the atom's own-direction sum sum_j h_ij, its
+// virial -sum_j r_ij (x) h_ij, and -h_ij written into the slot of the reverse
+// pair (j, i), so that k_force_gather completes F_j = sum h_jk + sum (-h_kj)
+// with contiguous reads and no atomics.
 template <typename R, class Sh, int S>
-__global__ void __launch_bounds__(kBlock)
-k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
-        const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-        const int* __restrict__ reverse, const R* __restrict__ A_in, const R* __restrict__ e_in,
-        Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D;
-    constexpr int TEAMS = kBlock / S;
-    __shared__ R Bsh[TEAMS][NA * LM];
-    const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
-    const bool live = i < Na;
+__device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __restrict__ theta, int i, bool live,
+                                           int a, const int64_t* __restrict__ row, const int* __restrict__ seg,
+                                           const Rec<R>* __restrict__ pairs, const int* __restrict__ reverse,
+                                           const R* Bk, const R* __restrict__ ei, Rec<R>* __restrict__ h_in,
+                                           R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
+    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
-    const int a = live ? types[i] : 0;
     int64_t p = live ? row[i] : 0;
-    const R* __restrict__ ei = e_in + (long)(live ? i : 0) * D;
-    if (live) {
-        moment_adjoints<R, Sh, S, false>(lane, A_in + (long)i * NA * LM, nullptr, ei, nullptr, Bsh[team], nullptr);
-    } else {
-        for (int x = lane; x < NA * LM; x += S) Bsh[team][x] = R(0);
-    }
-    __syncthreads();
-    const R* Bk = Bsh[team];
     R F[3] = {R(0), R(0), R(0)};
     R Wv[9];
 #pragma unroll
@@ -527,6 +548,32 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ type
         for (int c = 0; c < 9; ++c)
             if (c % S == lane) Wat_out[(long)i * 9 + c] = Wv[c];
     }
+}
+
+// Forces and virials (Eq. 1) in their own sweep: each team builds its atom's
+// B = dE_i/dA in LDS from the stored moments and e, then runs force_pass.
+template <typename R, class Sh, int S>
+__global__ void __launch_bounds__(kBlock)
+k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
+        const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
+        const int* __restrict__ reverse, const R* __restrict__ A_in, const R* __restrict__ e_in,
+        Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
+    constexpr int NA = Sh::NA, LM = Sh::LM, D = Sh::D;
+    constexpr int TEAMS = kBlock / S;
+    __shared__ R Bsh[TEAMS][NA * LM];
+    const int team = threadIdx.x / S, lane = threadIdx.x % S;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
+    const bool live = i < Na;
+    const int a = live ? types[i] : 0;
+    const R* __restrict__ ei = e_in + (long)(live ? i : 0) * D;
+    if (live) {
+        moment_adjoints<R, Sh, S, false>(lane, A_in + (long)i * NA * LM, nullptr, ei, nullptr, Bsh[team], nullptr);
+    } else {
+        for (int x = lane; x < NA * LM; x += S) Bsh[team][x] = R(0);
+    }
+    __syncthreads();
+    force_pass<R, Sh, S>(lane, dm, theta, i, live, a, row, seg, pairs, reverse, Bsh[team], ei, h_in, Fown_out,
+                         Wat_out);
 }
 
 // F_i = (own-direction sum) + sum_{p in row i} h_in[p]: team of S lanes per

@@ -43,18 +43,25 @@ nep_status run_shape(const Ctx& c) {
 
     R* q = (c.mode == Mode::Descriptors || c.desc_out) && c.desc_out ? static_cast<R*>(c.desc_out) : Wr(L.q);
     // network 3: each atom's network runs in its team at the end of the
-    // descriptor (forward) and tangent (Hessian-vector product) sweeps
+    // descriptor (forward) and tangent (Hessian-vector product) sweeps, and
+    // when forces are wanted the descriptor sweep also runs the force pass
     const bool fused = c.plan.network == 3 && c.mode != Mode::Descriptors;
+    const bool fused_force = fused && (c.mode == Mode::Forward || c.mode == Mode::LossGrad);
+    Rec<R>* hslots = reinterpret_cast<Rec<R>*>(Wr(L.h));
     if (Na > 0 && (rs = with_team(c.plan.team_desc, [&](auto S_) -> nep_status {
             constexpr int S = decltype(S_)::value;
-            if (fused)
-                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, true>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+            if (fused_force)
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 2>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
                            theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
-                           Wr(L.t));
+                           Wr(L.t), c.reverse, hslots, Wr(L.Fown), Wr(L.Wat));
+            else if (fused)
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 1>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+                           theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
+                           Wr(L.t), nullptr, nullptr, nullptr, nullptr);
             else
-                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, false>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 0>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
                            theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), nullptr, nullptr, nullptr,
-                           nullptr);
+                           nullptr, nullptr, nullptr, nullptr, nullptr);
             return NEP_OK;
         })))
         return rs;
@@ -77,9 +84,10 @@ nep_status run_shape(const Ctx& c) {
     if (c.mode == Mode::Forward || loss) {
         if (Na > 0 && (rs = with_team(c.plan.team_force, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
-                NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
-                           c.types, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e),
-                           reinterpret_cast<Rec<R>*>(Wr(L.h)), Wr(L.Fown), Wr(L.Wat));
+                if (!fused_force)
+                    NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
+                               c.types, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e), hslots, Wr(L.Fown),
+                               Wr(L.Wat));
                 NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, Na,
                            c.row, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
                 return NEP_OK;

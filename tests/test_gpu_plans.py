@@ -55,6 +55,12 @@ def test_plan_parity(which, plan):
     assert rel_err(g.double().cpu().numpy(), go) < t["G"]
     q = N.nep_descriptors(model, theta, gb, nb, ws)
     assert rel_err(q.double().cpu().numpy(), O.descriptors(m, th, b)) < t["F"]
+    # the forward-only call under the same plan (fused plans run the force
+    # pass inside the descriptor sweep there too)
+    E2, F2, W2 = N.nep_forward(model, theta, qs, gb, nb, ws)
+    assert rel_err(E2.cpu().numpy(), Eo) < t["E"]
+    assert rel_err(F2.double().cpu().numpy(), Fo) < t["F"]
+    assert rel_err(W2.cpu().numpy(), Wo) < t["F"]
 
 
 def test_autotune_returns_valid_plan():
