@@ -171,6 +171,10 @@ def measured_traffic(kernel, workload, plan=None):
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
     if not os.path.exists(path):
         return None
+    # the summary's row for this kernel as the plan builds it
+    label = "k_" + kernel
+    if plan is not None and plan.get("network") == 3 and kernel in ("descriptor", "tangent"):
+        label += "+network+force" if kernel == "descriptor" else "+network"
     digest, val = None, None
     for line in open(path):
         if line.startswith("plan:") and plan is not None:
@@ -180,7 +184,7 @@ def measured_traffic(kernel, workload, plan=None):
         if line.startswith("source-sha256:"):
             digest = line.split(":", 1)[1].strip()
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 6 and cells[0] in (kernel, "k_" + kernel):
+        if len(cells) >= 6 and cells[0] == label:
             try:
                 val = float(cells[5])
             except ValueError:
