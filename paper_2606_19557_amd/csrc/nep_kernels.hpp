@@ -50,7 +50,7 @@ template <typename R, int D, int S>
 __device__ __forceinline__ void team_network_forward(int lane, const Dims& dm, const R* __restrict__ theta, int a,
                                                      const R* __restrict__ qscale, const R (&qv)[D], long i,
                                                      R* __restrict__ E_out, R* __restrict__ e_out,
-                                                     R* __restrict__ t_out) {
+                                                     R* __restrict__ t_out, R (&e)[D]) {
     const int H = dm.H;
     const R* __restrict__ W0 = theta + dm.offN + (long)a * (D + 2) * H;
     const R* __restrict__ b0 = W0 + (long)H * D;
@@ -89,8 +89,10 @@ __device__ __forceinline__ void team_network_forward(int lane, const Dims& dm, c
     for (int v = 0; v < D; ++v) ev[v] = team_sum<S>(ev[v]);
     if (lane == 0) E_out[i] = E - theta[dm.offB1];
 #pragma unroll
-    for (int v = 0; v < D; ++v)
-        if (v % S == lane) e_out[i * D + v] = qscale[v] * ev[v];
+    for (int v = 0; v < D; ++v) {
+        e[v] = qscale[v] * ev[v];  // every lane
+        if (v % S == lane) e_out[i * D + v] = e[v];
+    }
 }
 
 // Loads of the first step of team_network_backward (units mu = lane and
@@ -198,12 +200,14 @@ __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __
                                            R* __restrict__ Fown_out, R* __restrict__ Wat_out);
 
 // LDS per team of the descriptor sweep: the moment exchange, grown when the
-// sweep also runs the force pass (the team's B = dE/dA, N_A x 24 values)
-// by whole 128-byte steps, so team blocks keep the exchange's bank pattern.
-template <typename R, int NA, int LM, int S, int FUSE>
+// sweep also runs the force pass (the team's B = dE/dA, N_A x 24 values,
+// and e's N_R radial entries) by whole 128-byte steps, so team blocks keep
+// the exchange's bank pattern.
+template <typename R, int NA, int LM, int NR, int S, int FUSE>
 struct DescTeamLds {
     static constexpr int TF = MomentExchange<R, NA, LM, S>::TEAM_FLOATS, STEP = 128 / int(sizeof(R));
-    static constexpr int floats = (FUSE < 2 || TF >= NA * LM) ? TF : TF + (NA * LM - TF + STEP - 1) / STEP * STEP;
+    static constexpr int need = NA * LM + NR;  // B, then e's radial entries
+    static constexpr int floats = (FUSE < 2 || TF >= need) ? TF : TF + (need - TF + STEP - 1) / STEP * STEP;
 };
 
 // ------------------------------------------------------------------ descriptor
@@ -224,7 +228,7 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
              Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
     constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D, L = Sh::L;
     using X = MomentExchange<R, NA, LM, S>;
-    constexpr int OWN = X::OWN, TEAMS = kBlock / S, XR = DescTeamLds<R, NA, LM, S, FUSE>::floats;
+    constexpr int OWN = X::OWN, TEAMS = kBlock / S, XR = DescTeamLds<R, NA, LM, NR, S, FUSE>::floats;
     __shared__ R xbuf[TEAMS * XR];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     R* tbuf = xbuf + team * XR;
@@ -348,17 +352,44 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
             const int lm = lane + S * o;
             if (lm < LM) A_out[((long)i * NA + n) * LM + lm] = acc[n][o];
         }
-    if (FUSE >= 1) team_network_forward<R, D, S>(lane, dm, theta, a, qscale, qv, i, E_out, e_out, t_out);
+    R e[D];
+    if (FUSE >= 1) team_network_forward<R, D, S>(lane, dm, theta, a, qscale, qv, i, E_out, e_out, t_out, e);
     if (FUSE == 2) {
-        // B from the team's just-stored A and e rows (a workgroup-scope fence
-        // makes each lane's stores visible to the other lanes), into the
-        // team's LDS block, whose exchange use has ended
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        moment_adjoints<R, Sh, S, false>(lane, A_out + (long)i * NA * LM, nullptr, e_out + (long)i * D, nullptr,
-                                         tbuf, nullptr);
-        X::wave_fence();
-        force_pass<R, Sh, S>(lane, dm, theta, i, true, a, row, seg, pairs, reverse, tbuf, e_out + (long)i * D, h_in,
-                             Fown_out, Wat_out);
+        // B = dE_i/dA into the team's LDS block, whose exchange use has ended
+        if constexpr (!Sh::H4 && !Sh::H5 && (Sh::NA * Sh::LM <= 120 || S >= 8)) {
+            // three-body invariants only: B_nlm = 2 e_(n,l) A_nlm, each lane
+            // for the harmonics it owns, from registers; e's radial entries
+            // beside it for the radial force coefficients (4-lane teams of
+            // large moment blocks would spill holding e)
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int o = 0; o < OWN; ++o) {
+                    const int lm = lane + S * o;
+                    if (lm >= LM) continue;
+                    const int l = lm < 3 ? 1 : lm < 8 ? 2 : lm < 15 ? 3 : 4;
+                    R el = e[NR + n];
+#pragma unroll
+                    for (int ll = 2; ll <= L; ++ll)
+                        if (l == ll) el = e[NR + (ll - 1) * NA + n];
+                    tbuf[n * LM + lm] = R(2) * el * acc[n][o];
+                }
+#pragma unroll
+            for (int d = 0; d < NR; ++d)
+                if (d % S == lane) tbuf[NA * LM + d] = e[d];
+            X::wave_fence();
+            force_pass<R, Sh, S>(lane, dm, theta, i, true, a, row, seg, pairs, reverse, tbuf, tbuf + NA * LM, h_in,
+                                 Fown_out, Wat_out);
+        } else {
+            // from the team's just-stored A and e rows (a workgroup-scope
+            // fence makes each lane's stores visible to the other lanes)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            moment_adjoints<R, Sh, S, false>(lane, A_out + (long)i * NA * LM, nullptr, e_out + (long)i * D, nullptr,
+                                             tbuf, nullptr);
+            X::wave_fence();
+            force_pass<R, Sh, S>(lane, dm, theta, i, true, a, row, seg, pairs, reverse, tbuf, e_out + (long)i * D,
+                                 h_in, Fown_out, Wat_out);
+        }
     }
 }
 
