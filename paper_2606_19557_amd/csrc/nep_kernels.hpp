@@ -1140,90 +1140,75 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
         // the next sub-chunk's atom indices, issued before this one's staging
         int nxt = 0;
         if (threadIdx.x < SC && s0 + SC + threadIdx.x < hi) nxt = order[s0 + SC + threadIdx.x];
-        // per-unit rows: contiguous in the species-sorted list, or (written by
-        // the sweeps) indexed by atom
-        for (int x0 = threadIdx.x; x0 < SC * H; x0 += U * kBlock) {
-            R va[U], vb[U], vg[U];
+        // One staging loop for every operand array: each thread first issues
+        // the loads of U iterations of all of them (slots past an array's
+        // end read its element 0 and are not stored), then stores them, so a
+        // sub-chunk costs one memory wait per thread, not one per array.
+        // Per-unit rows are contiguous in the species-sorted list, or
+        // (written by the sweeps) indexed by atom; per-atom rows are gathered
+        // by atom index.
+        const int nX = SC * H, nY = SC * D, nR = SC * NR, nC = SC * TK;
+        const int nMax = nX > nY ? (nX > nC ? nX : nC) : (nY > nC ? nY : nC);
+        for (int x0 = threadIdx.x; x0 < nMax; x0 += U * kBlock) {
+            R va[U], vb[U], vg[U], vq[U], vd[U], ra[U], re[U], c0[U], c1[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int x = x0 + u * kBlock;
-                const bool in = x < n * H;
-                const int sl = in ? x / H : 0, c = in ? x % H : 0;
-                const long src = units_by_atom ? long(os[sl]) * H + c : (s0 + sl) * H + c;
-                va[u] = alpha[src];
-                vb[u] = beta[src];
-                vg[u] = gam[src];
+                {
+                    const bool in = x < n * H;
+                    const int sl = in ? x / H : 0, c = in ? x % H : 0;
+                    const long src = units_by_atom ? long(os[sl]) * H + c : (s0 + sl) * H + c;
+                    va[u] = alpha[src];
+                    vb[u] = beta[src];
+                    vg[u] = gam[src];
+                }
+                {
+                    const bool in = x < n * D;
+                    const int v = in ? x % D : 0;
+                    const long i = os[in ? x / D : 0];
+                    const R sv = qscale[v];
+                    vq[u] = sv * q_in[i * D + v];
+                    vd[u] = sv * dq_in[i * D + v];
+                }
+                {
+                    const bool in = x < n * NR;
+                    const int r = in ? x % NR : 0;
+                    const long i = os[in ? x / NR : 0];
+                    ra[u] = abar[i * D + r];
+                    re[u] = e_in[i * D + r];
+                }
+                {
+                    const bool in = x < n * TK;
+                    const int c = in ? x % TK : 0;
+                    const long i = os[in ? x / TK : 0];
+                    c0[u] = S0[i * TK + c];
+                    c1[u] = S1[i * TK + c];
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int x = x0 + u * kBlock;
-                if (x >= SC * H) continue;
-                const bool in = x < n * H;
-                Xa[x] = in ? va[u] : R(0);
-                Xb[x] = in ? vb[u] : R(0);
-                Xg[x] = in ? vg[u] : R(0);
-            }
-        }
-        // per-atom rows, gathered by atom index
-        for (int x0 = threadIdx.x; x0 < SC * D; x0 += U * kBlock) {
-            R vq[U], vd[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = x0 + u * kBlock;
-                const bool in = x < n * D;
-                const int v = in ? x % D : 0;
-                const long i = os[in ? x / D : 0];
-                const R sv = qscale[v];
-                vq[u] = sv * q_in[i * D + v];
-                vd[u] = sv * dq_in[i * D + v];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = x0 + u * kBlock;
-                if (x >= SC * D) continue;
-                const bool in = x < n * D;
-                Yq[x] = in ? vq[u] : R(0);
-                Yd[x] = in ? vd[u] : R(0);
-            }
-        }
-        for (int x0 = threadIdx.x; x0 < SC * NR; x0 += U * kBlock) {
-            R va[U], ve[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = x0 + u * kBlock;
-                const bool in = x < n * NR;
-                const int r = in ? x % NR : 0;
-                const long i = os[in ? x / NR : 0];
-                va[u] = abar[i * D + r];
-                ve[u] = e_in[i * D + r];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = x0 + u * kBlock;
-                if (x >= SC * NR) continue;
-                const bool in = x < n * NR;
-                Ra[x] = in ? va[u] : R(0);
-                Re[x] = in ? ve[u] : R(0);
-            }
-        }
-        for (int x0 = threadIdx.x; x0 < SC * TK; x0 += U * kBlock) {
-            R v0[U], v1[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = x0 + u * kBlock;
-                const bool in = x < n * TK;
-                const int c = in ? x % TK : 0;
-                const long i = os[in ? x / TK : 0];
-                v0[u] = S0[i * TK + c];
-                v1[u] = S1[i * TK + c];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int x = x0 + u * kBlock;
-                if (x >= SC * TK) continue;
-                const bool in = x < n * TK;
-                C0[x] = in ? v0[u] : R(0);
-                C1[x] = in ? v1[u] : R(0);
+                if (x < nX) {
+                    const bool in = x < n * H;
+                    Xa[x] = in ? va[u] : R(0);
+                    Xb[x] = in ? vb[u] : R(0);
+                    Xg[x] = in ? vg[u] : R(0);
+                }
+                if (x < nY) {
+                    const bool in = x < n * D;
+                    Yq[x] = in ? vq[u] : R(0);
+                    Yd[x] = in ? vd[u] : R(0);
+                }
+                if (x < nR) {
+                    const bool in = x < n * NR;
+                    Ra[x] = in ? ra[u] : R(0);
+                    Re[x] = in ? re[u] : R(0);
+                }
+                if (x < nC) {
+                    const bool in = x < n * TK;
+                    C0[x] = in ? c0[u] : R(0);
+                    C1[x] = in ? c1[u] : R(0);
+                }
             }
         }
         if (threadIdx.x < SC) ord[buf ^ 1][threadIdx.x] = nxt;
