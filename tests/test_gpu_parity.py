@@ -255,3 +255,48 @@ def test_autograd_function_matches_loss_and_grad():
     loss, g = N.nep_loss_and_grad(model, theta, qs, gb, nb, N.Targets(*tg, dtype=torch.float64), ws)
     assert rel_err(th_t.grad.cpu().numpy(), g.cpu().numpy()) < 1e-10
     assert abs(L.item() - loss[0].item()) < 1e-12 * abs(L.item())
+
+
+# The fused plan (network inside the sweeps, force pass inside the descriptor
+# sweep) on every kernel shape, with the team sizes the autotuner picks there
+# and the other register / LDS variants of the fused force pass (from
+# registers for three-body models, through the stored rows for 4-lane teams of
+# large moment blocks and for 4/5-body models).
+FUSED = [
+    ("bcc64x8", None, "f64", (16, 16, 16, 32, 2048, 64, 3)),
+    ("alloy4_1024", [4, 0, 1, 3], "f32", (4, 4, 4, 8, 1024, 128, 3)),
+    ("mixed3_4096", [0, 1, 2, 4, 5], "f32", (8, 8, 8, 16, 2048, 64, 3)),
+    ("mixed3_4096", [0, 1, 2, 4, 5], "f32", (4, 4, 16, 32, 512, 32, 3)),
+    ("large5_32", [20], "f32", (4, 4, 8, 16, 1024, 128, 3)),
+    ("large5_32", [20], "f32", (16, 16, 4, 8, 4096, 256, 3)),
+]
+
+
+@pytest.mark.parametrize("name,idx,dtype,plan", FUSED)
+def test_fused_plan_parity(name, idx, dtype, plan):
+    _say(f"fused plan {name} {dtype} {plan}")
+    md, m, b, th, s, tg, model, gb, nb, ws, theta, qs = _setup(name, idx, dtype)
+    model = model.with_plan(N.Plan(*plan))
+    ws = N.workspace(model, gb, nb)
+    Et, Ft, Wt = tg
+    lam = (1.0, 1.0, 0.1)
+    targets = N.Targets(Et, Ft, Wt, lambdas=lam, dtype=model.torch_dtype)
+    loss, g, E, F, W = N.nep_loss_and_grad(model, theta, qs, gb, nb, targets, ws, want_predictions=True)
+    lo, go, Eo, Fo, Wo = O.loss_and_grad(m, th, s, b, Et, Ft, Wt, lam, nthreads=8)
+    tol = TOL[dtype]
+    assert rel_err(loss.cpu().numpy(), lo) < tol["L"]
+    assert rel_err(E.cpu().numpy(), Eo) < tol["E"]
+    assert rel_err(F.double().cpu().numpy(), Fo) < tol["F"]
+    assert rel_err(W.cpu().numpy(), Wo) < tol["W"]
+    assert rel_err(g.double().cpu().numpy(), go) < tol["G"]
+    E2, F2, W2 = N.nep_forward(model, theta, qs, gb, nb, ws)
+    assert rel_err(E2.cpu().numpy(), Eo) < tol["E"]
+    assert rel_err(F2.double().cpu().numpy(), Fo) < tol["F"]
+    assert rel_err(W2.cpu().numpy(), Wo) < tol["W"]
+    rng = np.random.default_rng(11)
+    dE = rng.normal(size=b.num_structures)
+    dF = rng.normal(size=(b.num_atoms, 3))
+    dW = rng.normal(size=(b.num_structures, 9))
+    gv = N.nep_backward(model, theta, qs, gb, nb, torch.tensor(dE, device="cuda"),
+                        torch.tensor(dF, device="cuda"), torch.tensor(dW, device="cuda"), ws)
+    assert rel_err(gv.double().cpu().numpy(), O.vjp(m, th, s, b, dE, dF, dW)) < tol["G"]
