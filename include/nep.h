@@ -77,7 +77,8 @@ typedef struct {
     int32_t network;           /* per-species network passes: 1 = matrix-core tiles of 32 atoms (16 in FP64),
                                   2 = one lane per atom in 64-atom wavefronts, weights as wave-uniform
                                   (scalar) operands; 3 = inside the descriptor and tangent sweeps, each
-                                  atom's team splitting the hidden units (no network launches); default 1 */
+                                  atom's team splitting the hidden units (no network launches), the
+                                  descriptor sweep then also running the force pass; default 1 */
 } nep_plan;
 
 /* Model hyper-parameters (the model keys of the paper's input file, Table I). */
