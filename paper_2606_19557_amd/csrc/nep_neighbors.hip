@@ -3,8 +3,8 @@
 // Each structure's cell is cut into n_d >= 1 bins along every lattice
 // direction d, each at least r_c wide across (n_d = floor(w_d / r_c), w_d the
 // perpendicular width), at most one bin per atom. Atoms are binned by their
-// wrapped fractional coordinates; a bin's atoms are kept in index order. One
-// lane per atom then scans the bins c + delta, |delta_d| <= ceil(r_c n_d / w_d):
+// wrapped fractional coordinates; a bin's atoms are kept in index order. A
+// team of lanes per atom then scans the bins c + delta, |delta_d| <= ceil(r_c n_d / w_d):
 // bin (c + delta) mod n lies in periodic image floor((c + delta) / n), so thin
 // cells (n_d = 1, w_d < r_c) get their extra images from the same loop, and
 // each (j, image) is visited once. Distances are tested in double precision.
@@ -187,6 +187,15 @@ k_bin_rank(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict_
 
 __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
 
+// One team of kNbTeam lanes per atom: the team walks the bins c + delta
+// together and splits each bin's atoms over its lanes, kNbTeam candidates at
+// a time in bin order. COUNT (FILL = false) writes the per-species
+// {all, angular} counts and the row length; FILL writes the records, each
+// (species, angular or not) group filled in candidate order: a lane's slot is
+// the group's cursor plus the hits of lower lanes in the same batch (team
+// ballots), so the rows are those of a scan of the bins one candidate at a time.
+constexpr int kNbTeam = 16;
+
 template <typename R, bool FILL>
 __global__ void __launch_bounds__(kNbBlock)
 k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restrict__ cells, double rcR,
@@ -194,8 +203,12 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
             const double* __restrict__ wpos, const int* __restrict__ sbins, const int64_t* __restrict__ bin_base,
             const int64_t* __restrict__ bin_start, const int* __restrict__ bin_atoms, int* __restrict__ seg,
             int64_t* __restrict__ count_or_row, Rec<R>* __restrict__ pairs) {
-    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
-    if (i >= Na) return;
+    constexpr int S = kNbTeam, TEAMS = kNbBlock / S;
+    const int team = threadIdx.x / S, lane = threadIdx.x % S;
+    const long i = (long)blockIdx.x * TEAMS + team;
+    if (i >= Na) return;  // whole teams
+    const int tshift = (threadIdx.x & 63) / S * S;  // the team's first bit in a wave ballot
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int s = atom_struct[i];
     const CellInfo ci = cell_info(cells + 9L * s);
     const int nb[3] = {sbins[3 * s], sbins[3 * s + 1], sbins[3 * s + 2]};
@@ -211,18 +224,21 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
     for (int d = 0; d < 3; ++d) kk[d] = int(ceil(rcR * nb[d] / ci.w[d] + 1e-9));
     const double ri[3] = {wpos[3 * i], wpos[3 * i + 1], wpos[3 * i + 2]};
     const double rc2R = rcR * rcR, rc2A = rcA * rcA;
-    int cur[2 * kMaxTypes];  // FILL: write cursors {angular, radial-only} per species
+    // per species {angular, radial-only}: FILL write cursors, COUNT {all, angular} counts
+    int cur[2 * kMaxTypes];
     int64_t base = 0;
+#pragma unroll
+    for (int b = 0; b < 2 * kMaxTypes; ++b) cur[b] = 0;
     if (FILL) {
         base = count_or_row[i];
         int acc = 0;
-        for (int b = 0; b < T; ++b) {
+#pragma unroll
+        for (int b = 0; b < kMaxTypes; ++b) {
+            if (b >= T) break;
             cur[2 * b] = acc;
             cur[2 * b + 1] = acc + seg[(i * T + b) * 2 + 1];
             acc += seg[(i * T + b) * 2];
         }
-    } else {
-        for (int b = 0; b < 2 * T; ++b) cur[b] = 0;
     }
     for (int d0 = -kk[0]; d0 <= kk[0]; ++d0) {
         const int t0 = c[0] + d0, m0 = floordiv(t0, nb[0]), b0 = t0 - m0 * nb[0];
@@ -234,37 +250,57 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
                 for (int x = 0; x < 3; ++x) sh[x] = m0 * ci.H[x] + m1 * ci.H[3 + x] + m2 * ci.H[6 + x] - ri[x];
                 const bool self_image = m0 == 0 && m1 == 0 && m2 == 0;
                 const long gb = bin_base[s] + (long(b0) * nb[1] + b1) * nb[2] + b2;
-                for (int64_t q = bin_start[gb]; q < bin_start[gb + 1]; ++q) {
-                    const int j = bin_atoms[q];
-                    if (self_image && j == i) continue;
-                    double r[3];
-                    for (int x = 0; x < 3; ++x) r[x] = wpos[3L * j + x] + sh[x];
-                    const double d2v = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                    if (!(d2v < rc2R)) continue;
-                    const bool ang = d2v < rc2A;
-                    const int tb = types[j];
-                    if (FILL) {
-                        const int slot = ang ? cur[2 * tb]++ : cur[2 * tb + 1]++;
-                        Rec<R> rec;
-                        rec.x = R(r[0]);
-                        rec.y = R(r[1]);
-                        rec.z = R(r[2]);
-                        if constexpr (sizeof(R) == 4)
-                            rec.w = __int_as_float(j);
-                        else
-                            rec.w = __longlong_as_double((long long)j);
-                        pairs[base + slot] = rec;
-                    } else {
-                        cur[2 * tb] += 1;
-                        if (ang) cur[2 * tb + 1] += 1;
+                const int64_t q1 = bin_start[gb + 1];
+                for (int64_t qb = bin_start[gb]; qb < q1; qb += S) {
+                    const int64_t q = qb + lane;
+                    bool hit = false, ang = false;
+                    int tb = -1, j = 0;
+                    double r[3] = {0.0, 0.0, 0.0};
+                    if (q < q1) {
+                        j = bin_atoms[q];
+                        if (!(self_image && j == i)) {
+                            for (int x = 0; x < 3; ++x) r[x] = wpos[3L * j + x] + sh[x];
+                            const double d2v = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                            hit = d2v < rc2R;
+                            ang = d2v < rc2A;
+                            if (hit) tb = types[j];
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < kMaxTypes; ++b) {
+                        if (b >= T) break;
+                        const unsigned long long ma = (__ballot(tb == b && ang) >> tshift) & ((1ull << S) - 1ull);
+                        const unsigned long long mr = (__ballot(tb == b && !ang) >> tshift) & ((1ull << S) - 1ull);
+                        if (FILL) {
+                            if (tb == b) {
+                                const int slot = ang ? cur[2 * b] + __popcll(ma & below)
+                                                     : cur[2 * b + 1] + __popcll(mr & below);
+                                Rec<R> rec;
+                                rec.x = R(r[0]);
+                                rec.y = R(r[1]);
+                                rec.z = R(r[2]);
+                                if constexpr (sizeof(R) == 4)
+                                    rec.w = __int_as_float(j);
+                                else
+                                    rec.w = __longlong_as_double((long long)j);
+                                pairs[base + slot] = rec;
+                            }
+                            cur[2 * b] += __popcll(ma);
+                            cur[2 * b + 1] += __popcll(mr);
+                        } else {
+                            cur[2 * b] += __popcll(ma) + __popcll(mr);
+                            cur[2 * b + 1] += __popcll(ma);
+                        }
                     }
                 }
             }
         }
     }
-    if (!FILL) {
+    if (!FILL && lane == 0) {
         int64_t tot = 0;
-        for (int b = 0; b < T; ++b) {
+#pragma unroll
+        for (int b = 0; b < kMaxTypes; ++b) {
+            if (b >= T) break;
             seg[(i * T + b) * 2] = cur[2 * b];
             seg[(i * T + b) * 2 + 1] = cur[2 * b + 1];
             tot += cur[2 * b];
@@ -571,6 +607,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     hipStream_t st = c.stream;
     const R* pos = static_cast<const R*>(b->positions);
     const int grid = int((Na + kNbBlock - 1) / kNbBlock);
+    const int team_grid = int((Na + kNbBlock / kNbTeam - 1) / (kNbBlock / kNbTeam));
     // Host-side validation of the index arrays every later kernel trusts:
     // offsets must run 0 .. Na without decreasing and species must lie in [0, T).
     {
@@ -618,7 +655,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                    bin_tmp);
         NEP_LAUNCH("cell_rank", k_bin_rank, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, bin_tmp,
                    bin_atoms);
-        NEP_LAUNCH("neighbors_count", (k_neighbors<R, false>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+        NEP_LAUNCH("neighbors_count", (k_neighbors<R, false>), dim3(team_grid), dim3(kNbBlock), 0, st, Na, T, b->types,
                    b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
                    bin_atoms, nb->seg_count, nb->row_offset, (Rec<R>*)nullptr);
     }
@@ -637,7 +674,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                     (long long)host_tot[0], (long long)nb->capacity);
     }
     if (Na > 0 && host_tot[0] > 0) {
-        NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+        NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(team_grid), dim3(kNbBlock), 0, st, Na, T, b->types,
                    b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
                    bin_atoms, nb->seg_count, nb->row_offset, static_cast<Rec<R>*>(nb->pairs));
         const long np = host_tot[0];
