@@ -197,6 +197,33 @@ nep_status nep_forward(const nep_model* model, const void* theta, const void* q_
                        const nep_neighbors* nbr, double* energy, void* force, double* virial, void* descriptor,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ZBL short-range repulsion (the screened-Coulomb correction the paper lists
+ * among NEP's supported terms; Methods). The form is the universal potential
+ * of Ziegler, Biersack and Littmark:
+ *   phi(r) = k_e Z_a Z_b / r * sum_k c_k exp(-d_k r / a_ab),
+ *   a_ab = 0.8854 a_0 / (Z_a^0.23 + Z_b^0.23),
+ *   (c, d) = (0.18175, 3.19980), (0.50986, 0.94229), (0.28022, 0.40290), (0.02817, 0.20162),
+ * k_e = 14.399645 eV A, a_0 = 0.529177210903 A, times the switch f(r) = 1 below
+ * r_inner, (1 + cos(pi (r - r_inner) / (r_outer - r_inner))) / 2 up to r_outer,
+ * 0 beyond. Atom i takes E_i = 1/2 sum_j phi(r_ij); forces and virials follow
+ * the conventions of nep_forward. The term has no trainable parameter. */
+typedef struct {
+    const int32_t* atomic_number; /* host [T] nuclear charge of each species, 1..118; read during the call */
+    double r_inner, r_outer;      /* switch range (Angstrom), 0 <= r_inner < r_outer <= model rc_r */
+} nep_zbl;
+
+/* Adds scale * (E, F, W) of the ZBL term to energy [Ns] (double), force
+ * [Na][3] (dtype) and virial [Ns][9] (double); any of the three may be NULL.
+ * scale = +1 after nep_forward gives NEP + ZBL predictions; scale = -1 on a
+ * dataset's targets once makes nep_loss_and_grad train NEP + ZBL (the loss and
+ * its gradient are unchanged by moving a parameter-free term to the targets).
+ * Pairs come from the radial lists of nep_build_neighbors; a pair at distance
+ * 0 contributes nothing. Deterministic (fixed summation order). ws: at least
+ * 80 * num_atoms bytes (per-atom partial sums). */
+nep_status nep_zbl_add(const nep_model* model, const nep_zbl* zbl, const nep_batch* batch, const nep_neighbors* nbr,
+                       double scale, double* energy, void* force, double* virial, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* The weighted loss L = lambda_e Delta_E + lambda_f Delta_F + lambda_v Delta_V
  * (Eqs. 4-7; N_s, N_a, N_a^s over the batch; Delta_V over labelled structures)
  * and its gradient dL/dtheta (the g_t of Adam, Eq. 8), computed analytically.

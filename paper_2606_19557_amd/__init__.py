@@ -10,6 +10,7 @@ from .nep import (  # noqa: F401
     NepError,
     Plan,
     Targets,
+    Zbl,
     nep_adam_step,
     nep_autotune,
     nep_backward,
@@ -23,5 +24,6 @@ from .nep import (  # noqa: F401
     nep_profile_enable,
     nep_profile_read,
     nep_workspace_size,
+    nep_zbl_add,
     workspace,
 )

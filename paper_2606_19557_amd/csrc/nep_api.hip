@@ -393,6 +393,32 @@ nep_status nep_forward(const nep_model* model, const void* theta, const void* q_
     return dispatch(c, se);
 }
 
+nep_status nep_zbl_add(const nep_model* model, const nep_zbl* zbl, const nep_batch* batch, const nep_neighbors* nbr,
+                       double scale, double* energy, void* force, double* virial, void* ws, size_t ws_bytes,
+                       void* stream) {
+    clear_error();
+    Dims dm;
+    nep_status s;
+    if ((s = make_dims(model, &dm))) return s;
+    if ((s = check_batch(batch))) return s;
+    if ((s = check_nbr(nbr, batch))) return s;
+    if (!zbl || !zbl->atomic_number) return fail(NEP_ERR_INVALID_ARG, "zbl or its atomic numbers is NULL");
+    for (int t = 0; t < dm.T; ++t)
+        if (zbl->atomic_number[t] < 1 || zbl->atomic_number[t] > 118)
+            return fail(NEP_ERR_INVALID_ARG, "atomic number %d of species %d outside [1, 118]",
+                        zbl->atomic_number[t], t);
+    if (!(zbl->r_inner >= 0.0) || !(zbl->r_outer > zbl->r_inner) || !(zbl->r_outer <= model->rc_r))
+        return fail(NEP_ERR_INVALID_ARG, "need 0 <= r_inner < r_outer <= rc_r (got %g, %g, rc_r %g)", zbl->r_inner,
+                    zbl->r_outer, model->rc_r);
+    if (!std::isfinite(scale)) return fail(NEP_ERR_INVALID_ARG, "scale must be finite");
+    const long Na = long(batch->num_atoms);
+    if (Na > 0 && !ws) return fail(NEP_ERR_INVALID_ARG, "workspace is NULL");
+    if (ws_bytes < zbl_workspace_bytes(Na))
+        return fail(NEP_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, zbl_workspace_bytes(Na));
+    return zbl_add(dm, model->dtype == NEP_F64, zbl, batch, nbr, scale, energy, force, virial, ws,
+                   static_cast<hipStream_t>(stream));
+}
+
 nep_status nep_loss_and_grad(const nep_model* model, const void* theta, const void* q_scale, const nep_batch* batch,
                              const nep_neighbors* nbr, const nep_targets* tg, double* loss, void* grad, double* energy,
                              void* force, double* virial, void* ws, size_t ws_bytes, void* stream) {

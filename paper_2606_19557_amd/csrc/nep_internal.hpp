@@ -152,4 +152,10 @@ nep_status gather_batch(const Ctx& c, const nep_batch* src, const nep_neighbors*
                         double* dst_cells, nep_neighbors* dn, double* dst_E, void* dst_F, double* dst_W,
                         uint8_t* dst_hv, void* ws, size_t ws_bytes);
 
+// ZBL pair term (nep_zbl.hip): adds scale * (E, F, W) of the term; arguments
+// already validated. ws holds zbl_workspace_bytes(Na).
+size_t zbl_workspace_bytes(long Na);
+nep_status zbl_add(const Dims& dm, bool f64, const nep_zbl* z, const nep_batch* b, const nep_neighbors* nb,
+                   double scale, double* energy, void* force, double* virial, void* ws, hipStream_t st);
+
 }  // namespace nep

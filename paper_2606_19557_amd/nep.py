@@ -22,7 +22,7 @@ NEP_F32, NEP_F64 = 0, 1
 
 EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_gather_batch", "nep_forward",
            "nep_loss_and_grad", "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale",
-           "nep_last_error", "nep_profile_enable", "nep_profile_read")
+           "nep_last_error", "nep_profile_enable", "nep_profile_read", "nep_zbl_add")
 
 
 class NepError(RuntimeError):
@@ -68,6 +68,10 @@ class c_adam(C.Structure):
                 ("amsgrad", C.c_int32), ("amsgrad_mode", C.c_int32)]
 
 
+class c_zbl(C.Structure):
+    _fields_ = [("atomic_number", C.POINTER(C.c_int32)), ("r_inner", C.c_double), ("r_outer", C.c_double)]
+
+
 _lib = None
 
 
@@ -96,6 +100,8 @@ def lib():
                                    C.POINTER(c_targets), vp, vp, vp, C.c_size_t, i32, C.POINTER(c_plan), vp]
         L.nep_adam_step.argtypes = [i64, i32, vp, vp, vp, vp, vp, i64, C.POINTER(c_adam), vp]
         L.nep_descriptor_scale.argtypes = [i64, i64, i32, vp, vp, vp]
+        L.nep_zbl_add.argtypes = [C.POINTER(c_model), C.POINTER(c_zbl), C.POINTER(c_batch), C.POINTER(c_neighbors),
+                                  C.c_double, vp, vp, vp, vp, C.c_size_t, vp]
         L.nep_last_error.restype = C.c_char_p
         L.nep_profile_enable.argtypes = [i32]
         L.nep_profile_read.argtypes = [i32, vp, vp, vp, C.POINTER(i32)]
@@ -340,6 +346,31 @@ def nep_forward(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, ws=N
     _check(lib().nep_forward(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), _ptr(E), _ptr(F),
                              _ptr(W), _ptr(q), _ptr(ws), ws.numel(), _stream()))
     return (E, F, W, q) if want_descriptor else (E, F, W)
+
+
+@dataclass(frozen=True)
+class Zbl:
+    """ZBL pair term: nuclear charge of each species and the switch range (A)."""
+
+    atomic_numbers: tuple
+    r_inner: float
+    r_outer: float
+
+
+def nep_zbl_add(model: Model, zbl: Zbl, batch: Batch, nbr: Neighbors, energy=None, force=None, virial=None,
+                scale: float = 1.0, ws=None):
+    """Adds scale * (E, F, W) of the ZBL term to the given tensors in place
+    (energy [Ns] f64, force [Na,3] model dtype, virial [Ns,9] f64; any may be None)."""
+    if len(zbl.atomic_numbers) != model.num_types:
+        raise ValueError(f"{len(zbl.atomic_numbers)} atomic numbers for {model.num_types} species")
+    dev = batch.positions.device
+    need = 80 * batch.num_atoms
+    ws = ws if ws is not None and ws.numel() >= need else torch.empty(max(need, 8), dtype=torch.uint8, device=dev)
+    z = (C.c_int32 * max(1, model.num_types))(*[int(v) for v in zbl.atomic_numbers])
+    cz = c_zbl(C.cast(z, C.POINTER(C.c_int32)), float(zbl.r_inner), float(zbl.r_outer))
+    m, b, cn = model.c(), batch.c(), nbr.c()
+    _check(lib().nep_zbl_add(C.byref(m), C.byref(cz), C.byref(b), C.byref(cn), float(scale), _ptr(energy),
+                             _ptr(force), _ptr(virial), _ptr(ws), ws.numel(), _stream()))
 
 
 def nep_descriptors(model: Model, theta, batch: Batch, nbr: Neighbors, ws=None):

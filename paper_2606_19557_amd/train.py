@@ -15,8 +15,8 @@ from dataclasses import asdict, dataclass, field
 import numpy as np
 import torch
 
-from .nep import (AdamConfig, Batch, Model, Targets, nep_adam_step, nep_build_neighbors, nep_gather_batch,
-                  nep_loss_and_grad, nep_param_count, nep_workspace_size)
+from .nep import (AdamConfig, Batch, Model, Targets, Zbl, nep_adam_step, nep_build_neighbors, nep_gather_batch,
+                  nep_loss_and_grad, nep_param_count, nep_workspace_size, nep_zbl_add)
 
 
 class Dataset:
@@ -25,10 +25,17 @@ class Dataset:
     (kept on the host, so packing a minibatch needs no device read-back)."""
 
     def __init__(self, model: Model, host_batch, energy, force, virial, has_virial=None, device="cuda",
-                 capacity: int | None = None):
+                 capacity: int | None = None, zbl: Zbl | None = None):
         batch = Batch.from_host(host_batch, dtype=model.torch_dtype, device=device)
         nbr = nep_build_neighbors(model, batch, capacity)
         targets = Targets(energy, force, virial, has_virial, dtype=model.torch_dtype, device=device)
+        if zbl is not None:
+            # the ZBL term has no parameter: training NEP on targets minus ZBL is
+            # training NEP + ZBL on the targets (same residuals, loss, gradient);
+            # the copies keep the caller's tensors unchanged
+            targets.energy, targets.force, targets.virial = (t.clone() for t in
+                                                             (targets.energy, targets.force, targets.virial))
+            nep_zbl_add(model, zbl, batch, nbr, targets.energy, targets.force, targets.virial, scale=-1.0)
         self._init(model, batch, nbr, targets, host_batch.atom_offset)
 
     @classmethod

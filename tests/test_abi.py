@@ -148,3 +148,28 @@ def test_gather_and_autotune_validate_before_launching():
     assert rc == nep.NEP_ERR_INVALID_ARG
     rc = L.nep_autotune(C.byref(m), vp, vp, C.byref(batch), C.byref(nb), None, vp, vp, vp, 1 << 20, 3, None, None)
     assert rc == nep.NEP_ERR_INVALID_ARG
+
+
+def test_zbl_validates_before_launching():
+    """The ZBL entry point rejects bad charges, switch ranges and workspaces on the host."""
+    L = _lib_or_skip()
+    m = nep.Model(num_types=2, rc_r=5.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30).c()
+    batch = nep.c_batch(1, 4, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8))
+    nb = nep.c_neighbors(16, *([C.c_void_p(8)] * 7), 8, 4)
+    vp = C.c_void_p(8)
+
+    def call(z, r_in, r_out, ws_bytes=320, scale=1.0):
+        zs = (C.c_int32 * 2)(*z)
+        cz = nep.c_zbl(C.cast(zs, C.POINTER(C.c_int32)), r_in, r_out)
+        return L.nep_zbl_add(C.byref(m), C.byref(cz), C.byref(batch), C.byref(nb), scale, vp, vp, vp, vp, ws_bytes,
+                             None)
+
+    assert call((26, 0), 1.0, 2.0) == nep.NEP_ERR_INVALID_ARG and b"atomic number" in L.nep_last_error()
+    assert call((26, 119), 1.0, 2.0) == nep.NEP_ERR_INVALID_ARG
+    assert call((26, 28), 2.0, 2.0) == nep.NEP_ERR_INVALID_ARG  # empty switch range
+    assert call((26, 28), -0.5, 2.0) == nep.NEP_ERR_INVALID_ARG
+    assert call((26, 28), 1.0, 5.5) == nep.NEP_ERR_INVALID_ARG and b"rc_r" in L.nep_last_error()
+    assert call((26, 28), 1.0, 2.0, scale=float("nan")) == nep.NEP_ERR_INVALID_ARG
+    assert call((26, 28), 1.0, 2.0, ws_bytes=319) == nep.NEP_ERR_WORKSPACE  # 80 bytes per atom
+    rc = L.nep_zbl_add(C.byref(m), None, C.byref(batch), C.byref(nb), 1.0, vp, vp, vp, vp, 320, None)
+    assert rc == nep.NEP_ERR_INVALID_ARG
