@@ -319,9 +319,27 @@ template <typename R>
 __global__ void __launch_bounds__(kNbBlock)
 k_reverse(long Na, long npairs, int T, const int* __restrict__ types, const int* __restrict__ seg,
           const int64_t* __restrict__ row, const Rec<R>* __restrict__ pairs, int* __restrict__ reverse) {
-    const long p = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    // The block's pairs belong to a short run of rows: two lanes find the rows
+    // of its first and last pair by bisection over all rows, every lane then
+    // bisects only inside that run (row[lo] <= p < row[hi] throughout).
+    __shared__ long run_s[2];
+    const long p0 = (long)blockIdx.x * kNbBlock;
+    const long p = p0 + threadIdx.x;
+    if (threadIdx.x < 2) {
+        const long key = threadIdx.x == 0 ? p0 : min(p0 + kNbBlock, npairs) - 1;
+        long lo = 0, hi = Na;
+        while (hi - lo > 1) {
+            const long mid = (lo + hi) >> 1;
+            if (row[mid] <= key)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        run_s[threadIdx.x] = lo;
+    }
+    __syncthreads();
     if (p >= npairs) return;
-    long lo = 0, hi = Na;  // row[lo] <= p < row[hi]
+    long lo = run_s[0], hi = run_s[1] + 1;
     while (hi - lo > 1) {
         const long mid = (lo + hi) >> 1;
         if (row[mid] <= p)
@@ -349,6 +367,169 @@ k_reverse(long Na, long npairs, int T, const int* __restrict__ types, const int*
         }
     }
     reverse[p] = (best >= 0 && bd < 1e-6) ? int(best) : -1;
+}
+
+// Multi-block form of the same exclusive scan, for long arrays: tiles of
+// kTile counts get their sums (k_tile_sums), a one-block scan turns those into
+// tile offsets (k_scan_counts on tile[0..ntiles]), and each tile then scans
+// itself from its offset (k_tile_apply). Every block touches only its own tile.
+constexpr int kTileThreads = 256, kTileItems = 8, kTile = kTileThreads * kTileItems;
+
+__device__ __forceinline__ int64_t block_sum_256(int64_t v, int64_t* part) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = v;
+    __syncthreads();
+    return part[0] + part[1] + part[2] + part[3];
+}
+
+// tile[b + 1] = sum of the counts a[1 + b*kTile ...]; with seg != nullptr
+// (the row scan) also adds the angular counts of the tile's atoms to *ang.
+__global__ void __launch_bounds__(kTileThreads)
+k_tile_sums(long n, const int64_t* __restrict__ a, int64_t* __restrict__ tile, int T, const int* __restrict__ seg,
+            unsigned long long* __restrict__ ang) {
+    __shared__ int64_t part[kTileThreads / 64];
+    const long base = (long)blockIdx.x * kTile;
+    int64_t s = 0, g = 0;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        const long i = base + k * kTileThreads + threadIdx.x;
+        if (i < n) {
+            s += a[i + 1];
+            if (seg)
+                for (int b = 0; b < T; ++b) g += seg[(i * T + b) * 2 + 1];
+        }
+    }
+    const int64_t tot = block_sum_256(s, part);
+    if (threadIdx.x == 0) tile[blockIdx.x + 1] = tot;
+    if (seg) {
+        __syncthreads();
+        const int64_t gt = block_sum_256(g, part);
+        if (threadIdx.x == 0) atomicAdd(ang, (unsigned long long)gt);
+    }
+}
+
+// a[1 + i] = tile offset + inclusive sum inside the tile; a[0] = 0. With
+// last != nullptr the grand total a[n] is also stored there.
+__global__ void __launch_bounds__(kTileThreads)
+k_tile_apply(long n, int64_t* __restrict__ a, const int64_t* __restrict__ tile, int64_t* __restrict__ last) {
+    __shared__ int64_t wsum[kTileThreads / 64];
+    const long i0 = (long)blockIdx.x * kTile + (long)threadIdx.x * kTileItems;
+    int64_t v[kTileItems], s = 0;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        v[k] = (i0 + k < n) ? a[i0 + k + 1] : 0;
+        s += v[k];
+    }
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    int64_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t run = tile[blockIdx.x] + incl - s;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        run += v[k];
+        if (i0 + k < n) {
+            a[i0 + k + 1] = run;
+            if (last && i0 + k == n - 1) *last = run;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a[0] = 0;
+}
+
+// Stable sort of atom indices by species over many blocks: one wavefront per
+// tile of kSortTile atoms counts each species with ballots, one block turns the
+// counts into each tile's first slot per species, and the wavefronts then
+// place their atoms in index order (slot = tile base + running count + rank
+// among the lower lanes with the same species). Same result as the one-block
+// sort below.
+constexpr int kSortTile = 1024;
+
+__global__ void __launch_bounds__(64)
+k_species_count(long Na, int T, const int* __restrict__ types, int* __restrict__ cnt) {
+    const long base = (long)blockIdx.x * kSortTile;
+    int c[kMaxTypes];
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t) c[t] = 0;
+    for (int st = 0; st < kSortTile / 64; ++st) {
+        const long i = base + st * 64 + threadIdx.x;
+        const int ty = i < Na ? types[i] : -1;
+#pragma unroll
+        for (int t = 0; t < kMaxTypes; ++t) {
+            if (t >= T) break;
+            c[t] += __popcll(__ballot(ty == t));
+        }
+    }
+    int mine = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t)
+        if ((int)threadIdx.x == t) mine = c[t];
+    if ((int)threadIdx.x < T) cnt[blockIdx.x * T + threadIdx.x] = mine;
+}
+
+// cnt[k][t] -> first slot of species t in tile k; soff[0..T] species starts.
+__global__ void __launch_bounds__(kScanBlock)
+k_species_base(long ntiles, int T, int* __restrict__ cnt, int64_t* __restrict__ soff) {
+    __shared__ int buf[kScanBlock];
+    __shared__ int tot_s[kMaxTypes + 1];
+    for (int t = 0; t < T; ++t) {
+        int carry = 0;
+        for (long b0 = 0; b0 < ntiles; b0 += kScanBlock) {
+            const long k = b0 + threadIdx.x;
+            const int v = k < ntiles ? cnt[k * T + t] : 0;
+            buf[threadIdx.x] = v;
+            __syncthreads();
+            for (int o = 1; o < kScanBlock; o <<= 1) {
+                const int x = (threadIdx.x >= (unsigned)o) ? buf[threadIdx.x - o] : 0;
+                __syncthreads();
+                buf[threadIdx.x] += x;
+                __syncthreads();
+            }
+            if (k < ntiles) cnt[k * T + t] = carry + buf[threadIdx.x] - v;
+            carry += buf[kScanBlock - 1];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot_s[t] = carry;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t o = 0;
+        for (int t = 0; t < T; ++t) {
+            const int c = tot_s[t];
+            soff[t] = o;
+            tot_s[t] = int(o);
+            o += c;
+        }
+        soff[T] = o;
+    }
+    __syncthreads();
+    for (long k = threadIdx.x; k < ntiles * T; k += kScanBlock) cnt[k] += tot_s[k % T];
+}
+
+__global__ void __launch_bounds__(64)
+k_species_scatter(long Na, int T, const int* __restrict__ types, const int* __restrict__ cnt, int* __restrict__ order) {
+    const long base = (long)blockIdx.x * kSortTile;
+    int run[kMaxTypes];
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t) run[t] = t < T ? cnt[blockIdx.x * T + t] : 0;
+    const unsigned long long below = (1ull << threadIdx.x) - 1ull;
+    for (int st = 0; st < kSortTile / 64; ++st) {
+        const long i = base + st * 64 + threadIdx.x;
+        const int ty = i < Na ? types[i] : -1;
+#pragma unroll
+        for (int t = 0; t < kMaxTypes; ++t) {
+            if (t >= T) break;
+            const unsigned long long m = __ballot(ty == t);
+            if (ty == t) order[run[t] + __popcll(m & below)] = (int)i;
+            run[t] += __popcll(m);
+        }
+    }
 }
 
 // Exclusive scan row[0..Na] of the per-row counts in row[1..Na] (row[0] = 0),
@@ -561,6 +742,8 @@ k_gather_pairs(long P, long Na, int n, const int* __restrict__ ids, const int64_
     dst_rev[p] = rv < 0 ? -1 : int(rv - src_row[src_off[sid]] + pair_base[k]);
 }
 
+nep_status species_sort(long Na, int T, const int* types, int* order, int64_t* soff, int* cnt, hipStream_t st);
+
 template <typename R>
 nep_status gather_impl(const Ctx& c, const nep_batch* src, const nep_neighbors* sn, const nep_targets* st_,
                        const int* ids, int n, long Na, int64_t* dst_off, void* dst_pos, int* dst_types,
@@ -593,8 +776,36 @@ nep_status gather_impl(const Ctx& c, const nep_batch* src, const nep_neighbors* 
         NEP_LAUNCH("gather_pairs", (k_gather_pairs<R>), dim3(int((P + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
                    st, P, Na, n, ids, src->atom_offset, sn->row_offset, static_cast<const Rec<R>*>(sn->pairs), sn->reverse,
                    dst_off, pair_base, dn->atom_struct, dn->row_offset, static_cast<Rec<R>*>(dn->pairs), dn->reverse);
-    NEP_LAUNCH("species_sort", k_species_sort, dim3(1), dim3(kScanBlock), 0, st, Na, T, dst_types, dn->species_order,
-               dn->species_offset);
+    return species_sort(Na, T, dst_types, dn->species_order, dn->species_offset, nullptr, st);
+}
+
+// Exclusive scan of a[1..n] in place (a[0] = 0); tile holds ceil(n / kTile) + 1 values.
+nep_status scan_counts(const char* name, long n, int64_t* a, int64_t* tile, hipStream_t st) {
+    const long ntiles = (n + kTile - 1) / kTile;
+    if (ntiles <= 1) {
+        NEP_LAUNCH(name, k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, n, a);
+        return NEP_OK;
+    }
+    NEP_LAUNCH(name, k_tile_sums, dim3(int(ntiles)), dim3(kTileThreads), 0, st, n, (const int64_t*)a, tile, 0,
+               (const int*)nullptr, (unsigned long long*)nullptr);
+    NEP_LAUNCH(name, k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, ntiles, tile);
+    NEP_LAUNCH(name, k_tile_apply, dim3(int(ntiles)), dim3(kTileThreads), 0, st, n, a, (const int64_t*)tile,
+               (int64_t*)nullptr);
+    return NEP_OK;
+}
+
+// Stable species sort; cnt (ceil(Na / kSortTile) * T ints) selects the
+// multi-block form, nullptr the one-block form.
+nep_status species_sort(long Na, int T, const int* types, int* order, int64_t* soff, int* cnt, hipStream_t st) {
+    const long ntiles = (Na + kSortTile - 1) / kSortTile;
+    if (!cnt || ntiles <= 4) {
+        NEP_LAUNCH("species_sort", k_species_sort, dim3(1), dim3(kScanBlock), 0, st, Na, T, types, order, soff);
+        return NEP_OK;
+    }
+    NEP_LAUNCH("species_sort", k_species_count, dim3(int(ntiles)), dim3(64), 0, st, Na, T, types, cnt);
+    NEP_LAUNCH("species_sort", k_species_base, dim3(1), dim3(kScanBlock), 0, st, ntiles, T, cnt, soff);
+    NEP_LAUNCH("species_sort", k_species_scatter, dim3(int(ntiles)), dim3(64), 0, st, Na, T, types,
+               (const int*)cnt, order);
     return NEP_OK;
 }
 
@@ -638,19 +849,22 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     int* bin_atoms = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
     int* bin_tmp = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
     double* wpos = reinterpret_cast<double*>(carve(sizeof(double) * 3 * size_t(Na)));
+    int64_t* tile = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (size_t(max_bins) / kTile + 2)));
+    int* sort_cnt = reinterpret_cast<int*>(carve(sizeof(int) * (size_t(Na) / kSortTile + 1) * size_t(T)));
     if (o > ws_bytes) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, the neighbour build needs %zu", ws_bytes, o);
     if (Na > 0) {
         const int sgrid = (Ns + kNbBlock - 1) / kNbBlock;
         const int bgrid = int((max_bins + 1 + kNbBlock - 1) / kNbBlock);
         NEP_LAUNCH("cell_setup", k_cell_setup, dim3(sgrid), dim3(kNbBlock), 0, st, Ns, b->atom_offset, b->cells,
                    c.dm.rcR, sbins, bin_base);
-        NEP_LAUNCH("cell_scan", k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, long(Ns), bin_base);
+        nep_status e;
+        if ((e = scan_counts("cell_scan", long(Ns), bin_base, tile, st))) return e;
         NEP_LAUNCH("cell_zero", k_zero<int64_t>, dim3(bgrid), dim3(kNbBlock), 0, st, max_bins + 1, bin_start);
         NEP_LAUNCH("cell_zero", k_zero<unsigned int>, dim3(bgrid), dim3(kNbBlock), 0, st, max_bins, cursor);
         NEP_LAUNCH("cell_bin", (k_bin_atoms<R>), dim3(grid), dim3(kNbBlock), 0, st, Ns, Na, b->atom_offset, pos,
                    b->cells, sbins, bin_base, nb->atom_struct, atom_bin, wpos,
                    reinterpret_cast<unsigned long long*>(bin_start));
-        NEP_LAUNCH("cell_scan", k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, max_bins, bin_start);
+        if ((e = scan_counts("cell_scan", max_bins, bin_start, tile, st))) return e;
         NEP_LAUNCH("cell_fill", k_bin_fill, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, cursor,
                    bin_tmp);
         NEP_LAUNCH("cell_rank", k_bin_rank, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, bin_tmp,
@@ -659,10 +873,25 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                    b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
                    bin_atoms, nb->seg_count, nb->row_offset, (Rec<R>*)nullptr);
     }
-    NEP_LAUNCH("neighbors_scan", k_scan_rows, dim3(1), dim3(kScanBlock), 0, st, Na, T, nb->row_offset, nb->seg_count,
-               totals);
-    NEP_LAUNCH("species_sort", k_species_sort, dim3(1), dim3(kScanBlock), 0, st, Na, T, b->types, nb->species_order,
-               nb->species_offset);
+    if (Na <= kTile) {
+        NEP_LAUNCH("neighbors_scan", k_scan_rows, dim3(1), dim3(kScanBlock), 0, st, Na, T, nb->row_offset,
+                   nb->seg_count, totals);
+    } else {
+        // row offsets over many blocks; totals[0] = pairs (the last offset),
+        // totals[1] = angular pairs (block sums added atomically, in integers)
+        const long ntiles = (Na + kTile - 1) / kTile;
+        NEP_LAUNCH("neighbors_scan", k_zero<int64_t>, dim3(1), dim3(kNbBlock), 0, st, 2L, totals);
+        NEP_LAUNCH("neighbors_scan", k_tile_sums, dim3(int(ntiles)), dim3(kTileThreads), 0, st, Na,
+                   (const int64_t*)nb->row_offset, tile, T, (const int*)nb->seg_count,
+                   reinterpret_cast<unsigned long long*>(totals + 1));
+        NEP_LAUNCH("neighbors_scan", k_scan_counts, dim3(1), dim3(kScanBlock), 0, st, ntiles, tile);
+        NEP_LAUNCH("neighbors_scan", k_tile_apply, dim3(int(ntiles)), dim3(kTileThreads), 0, st, Na, nb->row_offset,
+                   (const int64_t*)tile, totals);
+    }
+    {
+        nep_status e = species_sort(Na, T, b->types, nb->species_order, nb->species_offset, sort_cnt, st);
+        if (e) return e;
+    }
     int64_t host_tot[2] = {0, 0};
     NEP_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, st));
     NEP_HIP(hipStreamSynchronize(st));

@@ -110,3 +110,43 @@ def test_full_workload_sampled(name, sample):
         assert rel_err(E[st:st + 1], Eo) < 1e-5, st
         assert rel_err(F[a0:a1], Fo) < 1e-4, st
         assert rel_err(W[st], Wo) < 1e-4, st
+
+
+@pytest.mark.parametrize("name,sample", [("mixed3_4096", [0, 2047, 4095]), ("large5_32", [31])])
+def test_full_size_neighbor_lists(name, sample):
+    """Full-size neighbour build (many-block scans, species sort and reverse
+    search): invariants over every pair, and sampled structures' per-atom
+    counts against the oracle's brute-force search."""
+    _say(f"neighbors full {name}")
+    w = WORKLOADS[name]
+    host = workload_batch(name)
+    model = N.Model.from_dict(w.model, dtype=w.dtype)
+    gb = N.Batch.from_host(host, dtype=model.torch_dtype)
+    nb = N.nep_build_neighbors(model, gb)
+    torch.cuda.synchronize()
+    T, Na, P = w.model["num_types"], host.num_atoms, nb.num_pairs
+    row = nb.row_offset.cpu().numpy()
+    seg = nb.seg_count.cpu().numpy()
+    assert row[0] == 0 and row[-1] == P
+    assert np.array_equal(np.diff(row), seg[:, :, 0].sum(axis=1))
+    assert nb.num_angular_pairs == int(seg[:, :, 1].sum())
+    typ = np.asarray(host.types)
+    assert np.array_equal(nb.species_order.cpu().numpy(), np.argsort(typ, kind="stable"))
+    want_off = np.concatenate([[0], np.cumsum(np.bincount(typ, minlength=T))])
+    assert np.array_equal(nb.species_offset.cpu().numpy(), want_off)
+    owner = np.repeat(np.arange(Na), np.diff(row))
+    j = nb.neighbor_index().numpy()
+    rev = nb.reverse[:P].cpu().numpy().astype(np.int64)
+    r = nb.pairs[:P, :3].double().cpu().numpy()
+    ok = rev >= 0
+    assert ok.mean() > 0.9999  # a pair at the cutoff may lose its partner to rounding
+    p = np.nonzero(ok)[0]
+    q = rev[p]
+    assert np.array_equal(rev[q], p)
+    assert np.array_equal(owner[q], j[p]) and np.array_equal(j[q], owner[p])
+    assert np.abs(r[q] + r[p]).max() < 1e-4
+    for s in sample:
+        cell, pos, t = host.structure(s)
+        a0 = int(host.atom_offset[s])
+        oi, _, _, _ = O.neighbors(cell, pos, w.model["rc_r"])
+        assert np.array_equal(np.diff(row)[a0:a0 + len(pos)], np.bincount(oi, minlength=len(pos)))
