@@ -28,6 +28,13 @@ struct CellInfo {
     double H[9], Hi[9], w[3];
 };
 
+// An atom as the neighbour search reads it, stored in bin order: wrapped
+// position, index and species (one contiguous record per candidate).
+struct alignas(16) BinRec {
+    double x, y, z;
+    int j, t;
+};
+
 __device__ __forceinline__ CellInfo cell_info(const double* __restrict__ c) {
     CellInfo ci;
     for (int k = 0; k < 9; ++k) ci.H[k] = c[k];
@@ -172,17 +179,25 @@ k_bin_fill(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict_
 }
 
 // Each bin's atoms in increasing index order: atom i's rank in its bin is the
-// number of members with a smaller index (one lane per atom).
+// number of members with a smaller index (one lane per atom); its record goes
+// to that slot.
 __global__ void __launch_bounds__(kNbBlock)
 k_bin_rank(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
-           const int* __restrict__ bin_tmp, int* __restrict__ bin_atoms) {
+           const int* __restrict__ bin_tmp, const double* __restrict__ wpos, const int* __restrict__ types,
+           BinRec* __restrict__ bin_rec) {
     const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
     if (i >= Na) return;
     const int gb = atom_bin[i];
     const int64_t lo = bin_start[gb], hi = bin_start[gb + 1];
     int64_t rank = 0;
     for (int64_t q = lo; q < hi; ++q) rank += bin_tmp[q] < i;
-    bin_atoms[lo + rank] = int(i);
+    BinRec br;
+    br.x = wpos[3 * i];
+    br.y = wpos[3 * i + 1];
+    br.z = wpos[3 * i + 2];
+    br.j = int(i);
+    br.t = types[i];
+    bin_rec[lo + rank] = br;
 }
 
 __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
@@ -194,14 +209,16 @@ __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : 
 // (species, angular or not) group filled in candidate order: a lane's slot is
 // the group's cursor plus the hits of lower lanes in the same batch (team
 // ballots), so the rows are those of a scan of the bins one candidate at a time.
+// MT >= T bounds the per-species cursors (4, 8 or 16: fewer registers, more
+// waves per SIMD for batches with few species).
 constexpr int kNbTeam = 16;
 
-template <typename R, bool FILL>
+template <typename R, bool FILL, int MT>
 __global__ void __launch_bounds__(kNbBlock)
 k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restrict__ cells, double rcR,
             double rcA, const int* __restrict__ atom_struct, const int* __restrict__ atom_bin,
             const double* __restrict__ wpos, const int* __restrict__ sbins, const int64_t* __restrict__ bin_base,
-            const int64_t* __restrict__ bin_start, const int* __restrict__ bin_atoms, int* __restrict__ seg,
+            const int64_t* __restrict__ bin_start, const BinRec* __restrict__ bin_rec, int* __restrict__ seg,
             int64_t* __restrict__ count_or_row, Rec<R>* __restrict__ pairs) {
     constexpr int S = kNbTeam, TEAMS = kNbBlock / S;
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
@@ -225,15 +242,15 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
     const double ri[3] = {wpos[3 * i], wpos[3 * i + 1], wpos[3 * i + 2]};
     const double rc2R = rcR * rcR, rc2A = rcA * rcA;
     // per species {angular, radial-only}: FILL write cursors, COUNT {all, angular} counts
-    int cur[2 * kMaxTypes];
+    int cur[2 * MT];
     int64_t base = 0;
 #pragma unroll
-    for (int b = 0; b < 2 * kMaxTypes; ++b) cur[b] = 0;
+    for (int b = 0; b < 2 * MT; ++b) cur[b] = 0;
     if (FILL) {
         base = count_or_row[i];
         int acc = 0;
 #pragma unroll
-        for (int b = 0; b < kMaxTypes; ++b) {
+        for (int b = 0; b < MT; ++b) {
             if (b >= T) break;
             cur[2 * b] = acc;
             cur[2 * b + 1] = acc + seg[(i * T + b) * 2 + 1];
@@ -257,17 +274,20 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
                     int tb = -1, j = 0;
                     double r[3] = {0.0, 0.0, 0.0};
                     if (q < q1) {
-                        j = bin_atoms[q];
+                        const BinRec br = bin_rec[q];
+                        j = br.j;
                         if (!(self_image && j == i)) {
-                            for (int x = 0; x < 3; ++x) r[x] = wpos[3L * j + x] + sh[x];
+                            r[0] = br.x + sh[0];
+                            r[1] = br.y + sh[1];
+                            r[2] = br.z + sh[2];
                             const double d2v = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
                             hit = d2v < rc2R;
                             ang = d2v < rc2A;
-                            if (hit) tb = types[j];
+                            if (hit) tb = br.t;
                         }
                     }
 #pragma unroll
-                    for (int b = 0; b < kMaxTypes; ++b) {
+                    for (int b = 0; b < MT; ++b) {
                         if (b >= T) break;
                         const unsigned long long ma = (__ballot(tb == b && ang) >> tshift) & ((1ull << S) - 1ull);
                         const unsigned long long mr = (__ballot(tb == b && !ang) >> tshift) & ((1ull << S) - 1ull);
@@ -299,7 +319,7 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
     if (!FILL && lane == 0) {
         int64_t tot = 0;
 #pragma unroll
-        for (int b = 0; b < kMaxTypes; ++b) {
+        for (int b = 0; b < MT; ++b) {
             if (b >= T) break;
             seg[(i * T + b) * 2] = cur[2 * b];
             seg[(i * T + b) * 2 + 1] = cur[2 * b + 1];
@@ -309,19 +329,29 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
     }
 }
 
-// reverse[p] = index of the pair (j, i, -n) for pair p = (i, j, n): the entry
-// of row j with neighbour i whose vector is closest to -r_ij (exactly -r_ij up
-// to rounding; other images of the same atom differ by a lattice vector).
-// -1 if the reverse pair was not kept (possible only at |r_ij| = rc to rounding).
-// One lane per pair; the owning row is found by bisection of the row offsets
-// and only the group of row j holding neighbours of species type(i) is searched.
+// Reverse pair of every pair: p = (i -> j, image n) is matched with the pair
+// q = (j -> i, -n) in row j's group of species(i), the one with r_q = -r_p
+// (other images of i in that group differ from -r_p by a lattice vector, so
+// at most one record lies within 1e-3 A of it). One lane per pair, the group
+// read kRevBatch records at a time so that many loads are in flight. Each
+// unordered pair is searched once, from its end with the lower atom index,
+// which writes both reverse[p] and reverse[q]; pairs of an atom with its own
+// images search for themselves. reverse[] starts at -1 (k_fill), which stays
+// where no partner was kept (possible only at |r_ij| = r_c, to rounding).
+constexpr int kRevBatch = 8;
+
+__global__ void __launch_bounds__(kNbBlock) k_fill(long n, int v, int* __restrict__ a) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kNbBlock)
 k_reverse(long Na, long npairs, int T, const int* __restrict__ types, const int* __restrict__ seg,
           const int64_t* __restrict__ row, const Rec<R>* __restrict__ pairs, int* __restrict__ reverse) {
-    // The block's pairs belong to a short run of rows: two lanes find the rows
+    // the block's pairs belong to a short run of rows: two lanes find the rows
     // of its first and last pair by bisection over all rows, every lane then
-    // bisects only inside that run (row[lo] <= p < row[hi] throughout).
+    // bisects only inside that run (row[lo] <= p < row[hi] throughout)
     __shared__ long run_s[2];
     const long p0 = (long)blockIdx.x * kNbBlock;
     const long p = p0 + threadIdx.x;
@@ -348,25 +378,29 @@ k_reverse(long Na, long npairs, int T, const int* __restrict__ types, const int*
             hi = mid;
     }
     const long i = lo;
-    const int ti = types[i];
     const Rec<R> a = pairs[p];
     const long j = rec_j(a);
+    if (j < i) return;  // searched from the other end
+    const int ti = types[i];
     int64_t g0 = row[j];
     for (int b = 0; b < ti; ++b) g0 += seg[(j * T + b) * 2];
-    const int64_t g1 = g0 + seg[(j * T + ti) * 2];
-    int64_t best = -1;
-    double bd = 1e300;
-    for (int64_t q = g0; q < g1; ++q) {
-        const Rec<R> b = pairs[q];
-        if (rec_j(b) != i) continue;
-        const double dx = double(a.x) + double(b.x), dy = double(a.y) + double(b.y), dz = double(a.z) + double(b.z);
-        const double d = dx * dx + dy * dy + dz * dz;
-        if (d < bd) {
-            bd = d;
-            best = q;
+    const int n = seg[(j * T + ti) * 2];
+    long found = -1;
+    for (int base = 0; base < n && found < 0; base += kRevBatch) {
+        Rec<R> b[kRevBatch];
+#pragma unroll
+        for (int u = 0; u < kRevBatch; ++u) b[u] = pairs[g0 + min(base + u, n - 1)];  // in the group
+#pragma unroll
+        for (int u = 0; u < kRevBatch; ++u) {
+            if (base + u >= n || rec_j(b[u]) != i) continue;
+            const double dx = double(a.x) + double(b[u].x), dy = double(a.y) + double(b[u].y),
+                         dz = double(a.z) + double(b[u].z);
+            if (found < 0 && dx * dx + dy * dy + dz * dz < 1e-6) found = g0 + base + u;
         }
     }
-    reverse[p] = (best >= 0 && bd < 1e-6) ? int(best) : -1;
+    if (found < 0) return;
+    reverse[p] = int(found);
+    if (j != i) reverse[found] = int(p);
 }
 
 // Multi-block form of the same exclusive scan, for long arrays: tiles of
@@ -779,6 +813,13 @@ nep_status gather_impl(const Ctx& c, const nep_batch* src, const nep_neighbors* 
     return species_sort(Na, T, dst_types, dn->species_order, dn->species_offset, nullptr, st);
 }
 
+template <class F>
+nep_status with_max_types(int T, F&& f) {
+    if (T <= 4) return f(std::integral_constant<int, 4>{});
+    if (T <= 8) return f(std::integral_constant<int, 8>{});
+    return f(std::integral_constant<int, kMaxTypes>{});
+}
+
 // Exclusive scan of a[1..n] in place (a[0] = 0); tile holds ceil(n / kTile) + 1 values.
 nep_status scan_counts(const char* name, long n, int64_t* a, int64_t* tile, hipStream_t st) {
     const long ntiles = (n + kTile - 1) / kTile;
@@ -846,7 +887,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     int64_t* bin_start = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (size_t(max_bins) + 1)));
     unsigned int* cursor = reinterpret_cast<unsigned int*>(carve(sizeof(unsigned int) * size_t(max_bins)));
     int* atom_bin = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
-    int* bin_atoms = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
+    BinRec* bin_rec = reinterpret_cast<BinRec*>(carve(sizeof(BinRec) * size_t(Na)));
     int* bin_tmp = reinterpret_cast<int*>(carve(sizeof(int) * size_t(Na)));
     double* wpos = reinterpret_cast<double*>(carve(sizeof(double) * 3 * size_t(Na)));
     int64_t* tile = reinterpret_cast<int64_t*>(carve(sizeof(int64_t) * (size_t(max_bins) / kTile + 2)));
@@ -868,10 +909,15 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
         NEP_LAUNCH("cell_fill", k_bin_fill, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, cursor,
                    bin_tmp);
         NEP_LAUNCH("cell_rank", k_bin_rank, dim3(grid), dim3(kNbBlock), 0, st, Na, atom_bin, bin_start, bin_tmp,
-                   bin_atoms);
-        NEP_LAUNCH("neighbors_count", (k_neighbors<R, false>), dim3(team_grid), dim3(kNbBlock), 0, st, Na, T, b->types,
-                   b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
-                   bin_atoms, nb->seg_count, nb->row_offset, (Rec<R>*)nullptr);
+                   (const double*)wpos, b->types, bin_rec);
+        nep_status e2 = with_max_types(T, [&](auto mt) -> nep_status {
+            NEP_LAUNCH("neighbors_count", (k_neighbors<R, false, decltype(mt)::value>), dim3(team_grid),
+                       dim3(kNbBlock), 0, st, Na, T, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct,
+                       atom_bin, wpos, sbins, bin_base, bin_start, bin_rec, nb->seg_count, nb->row_offset,
+                       (Rec<R>*)nullptr);
+            return NEP_OK;
+        });
+        if (e2) return e2;
     }
     if (Na <= kTile) {
         NEP_LAUNCH("neighbors_scan", k_scan_rows, dim3(1), dim3(kScanBlock), 0, st, Na, T, nb->row_offset,
@@ -903,10 +949,17 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                     (long long)host_tot[0], (long long)nb->capacity);
     }
     if (Na > 0 && host_tot[0] > 0) {
-        NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true>), dim3(team_grid), dim3(kNbBlock), 0, st, Na, T, b->types,
-                   b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct, atom_bin, wpos, sbins, bin_base, bin_start,
-                   bin_atoms, nb->seg_count, nb->row_offset, static_cast<Rec<R>*>(nb->pairs));
+        nep_status e2 = with_max_types(T, [&](auto mt) -> nep_status {
+            NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true, decltype(mt)::value>), dim3(team_grid),
+                       dim3(kNbBlock), 0, st, Na, T, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct,
+                       atom_bin, wpos, sbins, bin_base, bin_start, bin_rec, nb->seg_count, nb->row_offset,
+                       static_cast<Rec<R>*>(nb->pairs));
+            return NEP_OK;
+        });
+        if (e2) return e2;
         const long np = host_tot[0];
+        NEP_LAUNCH("neighbors_reverse", k_fill, dim3(int((np + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0, st, np,
+                   -1, nb->reverse);
         NEP_LAUNCH("neighbors_reverse", (k_reverse<R>), dim3(int((np + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
                    st, Na, np, T, b->types, nb->seg_count, nb->row_offset, static_cast<const Rec<R>*>(nb->pairs),
                    nb->reverse);
