@@ -255,6 +255,10 @@ def main():
         data = Dataset.from_device(model, gb, nb, targets, host.atom_offset)
         order = np.random.Generator(np.random.PCG64(w.seed + 4000)).permutation(host.num_structures)
         mbs = [order[lo:lo + w.minibatch] for lo in range(0, len(order), w.minibatch)]
+        # the epoch's order goes to the device once (a copy from pageable host
+        # memory per step would wait for the previous step's kernels)
+        order_dev = torch.as_tensor(order.astype(np.int32)).to(dev)
+        mbs_dev = [order_dev[lo:lo + w.minibatch] for lo in range(0, len(order), w.minibatch)]
         sizes = np.array([data.sizes(ids) for ids in mbs])
         tune_b, tune_nb, tune_tg = data.minibatch(mbs[0])
         log(f"epoch of {len(mbs)} minibatches of {w.minibatch}: mean {sizes[:, 0].mean():.0f} atoms, "
@@ -301,7 +305,8 @@ def main():
 
     def step():
         if epoch_mode:
-            b_, nb_, tg_ = data.minibatch(mbs[step_no[0] % len(mbs)])
+            k = step_no[0] % len(mbs)
+            b_, nb_, tg_ = data.minibatch(mbs[k], ids_device=mbs_dev[k])
         else:
             b_, nb_, tg_ = gb, nb, targets
         N.nep_loss_and_grad(model, th, qs, b_, nb_, tg_, ws, grad=grad, loss=loss)

@@ -208,7 +208,8 @@ __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : 
 // {all, angular} counts and the row length; FILL writes the records, each
 // (species, angular or not) group filled in candidate order: a lane's slot is
 // the group's cursor plus the hits of lower lanes in the same batch (team
-// ballots), so the rows are those of a scan of the bins one candidate at a time.
+// ballots), so the rows are those of a scan of the bins one candidate at a time;
+// COUNT tallies per lane and sums over the team once at the end.
 // MT >= T bounds the per-species cursors (4, 8 or 16: fewer registers, more
 // waves per SIMD for batches with few species).
 constexpr int kNbTeam = 16;
@@ -286,34 +287,44 @@ k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restr
                             if (hit) tb = br.t;
                         }
                     }
+                    if (!FILL) {  // counting: per-lane tallies, summed over the team at the end
+#pragma unroll
+                        for (int b = 0; b < MT; ++b) {
+                            cur[2 * b] += tb == b;
+                            cur[2 * b + 1] += tb == b && ang;
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int b = 0; b < MT; ++b) {
                         if (b >= T) break;
                         const unsigned long long ma = (__ballot(tb == b && ang) >> tshift) & ((1ull << S) - 1ull);
                         const unsigned long long mr = (__ballot(tb == b && !ang) >> tshift) & ((1ull << S) - 1ull);
-                        if (FILL) {
-                            if (tb == b) {
-                                const int slot = ang ? cur[2 * b] + __popcll(ma & below)
-                                                     : cur[2 * b + 1] + __popcll(mr & below);
-                                Rec<R> rec;
-                                rec.x = R(r[0]);
-                                rec.y = R(r[1]);
-                                rec.z = R(r[2]);
-                                if constexpr (sizeof(R) == 4)
-                                    rec.w = __int_as_float(j);
-                                else
-                                    rec.w = __longlong_as_double((long long)j);
-                                pairs[base + slot] = rec;
-                            }
-                            cur[2 * b] += __popcll(ma);
-                            cur[2 * b + 1] += __popcll(mr);
-                        } else {
-                            cur[2 * b] += __popcll(ma) + __popcll(mr);
-                            cur[2 * b + 1] += __popcll(ma);
+                        if (tb == b) {
+                            const int slot = ang ? cur[2 * b] + __popcll(ma & below)
+                                                 : cur[2 * b + 1] + __popcll(mr & below);
+                            Rec<R> rec;
+                            rec.x = R(r[0]);
+                            rec.y = R(r[1]);
+                            rec.z = R(r[2]);
+                            if constexpr (sizeof(R) == 4)
+                                rec.w = __int_as_float(j);
+                            else
+                                rec.w = __longlong_as_double((long long)j);
+                            pairs[base + slot] = rec;
                         }
+                        cur[2 * b] += __popcll(ma);
+                        cur[2 * b + 1] += __popcll(mr);
                     }
                 }
             }
+        }
+    }
+    if (!FILL) {
+#pragma unroll
+        for (int b = 0; b < 2 * MT; ++b) {
+#pragma unroll
+            for (int o = 1; o < S; o <<= 1) cur[b] += __shfl_xor(cur[b], o, 64);
         }
     }
     if (!FILL && lane == 0) {
@@ -610,36 +621,64 @@ k_scan_rows(long Na, int T, int64_t* __restrict__ row, const int* __restrict__ s
     }
 }
 
-// Stable sort of atom indices by species, one block: each thread owns a
-// contiguous chunk, counts per species, and scatters after a block scan.
+// Stable sort of atom indices by species, one block: each of its wavefronts
+// owns a contiguous slice of whole 64-atom steps and counts each species with
+// ballots; one thread per species then sets where each wavefront's share of
+// it starts, and the wavefronts place their atoms in index order (rank among
+// the lower lanes of the same species from the same ballots).
 __global__ void __launch_bounds__(kScanBlock)
 k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ order, int64_t* __restrict__ soff) {
-    __shared__ int cnt[kScanBlock];
-    __shared__ int64_t tot_s[kMaxTypes + 1];
-    const long per = (Na + kScanBlock - 1) / kScanBlock;
-    const long c0 = threadIdx.x * per, c1 = min(Na, c0 + per);
-    if (threadIdx.x == 0) tot_s[0] = 0;
-    for (int t = 0; t < T; ++t) {
-        int c = 0;
-        for (long i = c0; i < c1; ++i) c += types[i] == t;
-        cnt[threadIdx.x] = c;
-        __syncthreads();
-        // inclusive scan of cnt
-        for (int o = 1; o < kScanBlock; o <<= 1) {
-            const int x = (threadIdx.x >= (unsigned)o) ? cnt[threadIdx.x - o] : 0;
-            __syncthreads();
-            cnt[threadIdx.x] += x;
-            __syncthreads();
+    constexpr int WAVES = kScanBlock / 64;
+    __shared__ int cnt_s[WAVES][kMaxTypes];
+    __shared__ int base_s[WAVES][kMaxTypes];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const long per = ((Na + WAVES - 1) / WAVES + 63) / 64 * 64;  // whole 64-atom steps per wave
+    const long a0 = min(Na, wave * per), a1 = min(Na, a0 + per);
+    int c[kMaxTypes];
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t) c[t] = 0;
+    for (long i0 = a0; i0 < a1; i0 += 64) {
+        const long i = i0 + lane;
+        const int ty = i < a1 ? types[i] : -1;
+#pragma unroll
+        for (int t = 0; t < kMaxTypes; ++t) {
+            if (t >= T) break;
+            c[t] += __popcll(__ballot(ty == t));
         }
-        const int64_t start = tot_s[t] + (cnt[threadIdx.x] - c);
-        int64_t w = start;
-        for (long i = c0; i < c1; ++i)
-            if (types[i] == t) order[w++] = (int)i;
-        __syncthreads();
-        if (threadIdx.x == kScanBlock - 1) tot_s[t + 1] = tot_s[t] + cnt[threadIdx.x];
-        __syncthreads();
     }
-    if (threadIdx.x <= (unsigned)T) soff[threadIdx.x] = tot_s[threadIdx.x];
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t)
+        if (lane == t && t < T) cnt_s[wave][t] = c[t];
+    __syncthreads();
+    // thread t: start of species t, then of each wave's share of it
+    if (threadIdx.x < (unsigned)T) {
+        const int t = threadIdx.x;
+        int64_t o = 0;
+        for (int u = 0; u < t; ++u)
+            for (int w = 0; w < WAVES; ++w) o += cnt_s[w][u];
+        soff[t] = o;
+        for (int w = 0; w < WAVES; ++w) {
+            base_s[w][t] = int(o);
+            o += cnt_s[w][t];
+        }
+        if (t == T - 1) soff[T] = o;
+    }
+    __syncthreads();
+    int run[kMaxTypes];
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t) run[t] = t < T ? base_s[wave][t] : 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (long i0 = a0; i0 < a1; i0 += 64) {
+        const long i = i0 + lane;
+        const int ty = i < a1 ? types[i] : -1;
+#pragma unroll
+        for (int t = 0; t < kMaxTypes; ++t) {
+            if (t >= T) break;
+            const unsigned long long m = __ballot(ty == t);
+            if (ty == t) order[run[t] + __popcll(m & below)] = (int)i;
+            run[t] += __popcll(m);
+        }
+    }
 }
 
 // ------------------------------------------------------------- minibatches
@@ -749,11 +788,31 @@ k_gather_pairs(long P, long Na, int n, const int* __restrict__ ids, const int64_
                const int* __restrict__ src_rev, const int64_t* __restrict__ dst_off,
                const int64_t* __restrict__ pair_base, const int* __restrict__ dst_struct,
                const int64_t* __restrict__ dst_row, Rec<R>* __restrict__ dst_pairs, int* __restrict__ dst_rev) {
-    const long p = (long)blockIdx.x * kNbBlock + threadIdx.x;
-    // rows 0 .. hi-1 were written by k_gather_atoms (hi <= the caller's Na)
+    // rows 0 .. hi0-1 were written by k_gather_atoms (hi0 <= the caller's Na);
+    // pairs 0 .. lim-1 lie inside them
     const long hi0 = Na < dst_off[n] ? Na : dst_off[n];
-    if (p >= P || p >= pair_base[n] || hi0 == 0 || p >= dst_row[hi0]) return;
-    long lo = 0, hi = hi0;  // dst_row[lo] <= p < dst_row[hi]
+    const long lim = hi0 == 0 ? 0 : min(min(P, (long)pair_base[n]), (long)dst_row[hi0]);
+    const long p0 = (long)blockIdx.x * kNbBlock;
+    if (p0 >= lim) return;  // the whole block
+    // the block's pairs lie in a short run of rows: two lanes bisect all rows for
+    // its first and last pair, every lane then bisects inside that run
+    __shared__ long run_s[2];
+    if (threadIdx.x < 2) {
+        const long key = threadIdx.x == 0 ? p0 : min(p0 + kNbBlock, lim) - 1;
+        long lo = 0, hi = hi0;
+        while (hi - lo > 1) {
+            const long mid = (lo + hi) >> 1;
+            if (dst_row[mid] <= key)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        run_s[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const long p = p0 + threadIdx.x;
+    if (p >= lim) return;
+    long lo = run_s[0], hi = run_s[1] + 1;  // dst_row[lo] <= p < dst_row[hi]
     while (hi - lo > 1) {
         const long mid = (lo + hi) >> 1;
         if (dst_row[mid] <= p)
@@ -839,7 +898,7 @@ nep_status scan_counts(const char* name, long n, int64_t* a, int64_t* tile, hipS
 // multi-block form, nullptr the one-block form.
 nep_status species_sort(long Na, int T, const int* types, int* order, int64_t* soff, int* cnt, hipStream_t st) {
     const long ntiles = (Na + kSortTile - 1) / kSortTile;
-    if (!cnt || ntiles <= 4) {
+    if (!cnt || ntiles <= 16) {
         NEP_LAUNCH("species_sort", k_species_sort, dim3(1), dim3(kScanBlock), 0, st, Na, T, types, order, soff);
         return NEP_OK;
     }

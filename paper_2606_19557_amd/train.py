@@ -63,10 +63,16 @@ class Dataset:
         ids = np.asarray(ids, dtype=np.int64)
         return int(self.atoms[ids].sum()), int(self.pairs[ids].sum()), int(self.angular[ids].sum())
 
-    def minibatch(self, ids, lambdas=None, ws=None):
-        """(Batch, Neighbors, Targets) of structures `ids`, packed on the device."""
+    def minibatch(self, ids, lambdas=None, ws=None, ids_device=None):
+        """(Batch, Neighbors, Targets) of structures `ids`, packed on the device.
+        `ids_device` may hold the same ids as a device int32 tensor: a copy from
+        pageable host memory waits for the stream's earlier work, so callers
+        stepping through an epoch upload its order once and pass slices."""
         na, npairs, nang = self.sizes(ids)
-        idt = torch.as_tensor(np.asarray(ids, dtype=np.int32)).to(self.batch.positions.device)
+        if ids_device is not None:
+            idt = ids_device
+        else:
+            idt = torch.as_tensor(np.asarray(ids, dtype=np.int32)).to(self.batch.positions.device)
         b, nb, tg = nep_gather_batch(self.model, self.batch, self.nbr, self.targets, idt, na, npairs, nang, ws)
         if lambdas is not None:
             tg.lambdas = tuple(float(x) for x in lambdas)
@@ -181,8 +187,9 @@ class Trainer:
         bs = self.cfg.batch_size
         acc = torch.zeros(4, dtype=torch.float64, device=self.theta.device)
         nmb = 0
+        order_dev = torch.as_tensor(np.asarray(order, dtype=np.int32)).to(self.theta.device)  # one copy per epoch
         for lo in range(0, len(order), bs):
-            b, nb, tg = data.minibatch(order[lo:lo + bs], lambdas=self.lambdas)
+            b, nb, tg = data.minibatch(order[lo:lo + bs], lambdas=self.lambdas, ids_device=order_dev[lo:lo + bs])
             self.step(b, nb, tg)
             acc += self.loss
             nmb += 1
