@@ -637,6 +637,7 @@ k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ 
     int c[kMaxTypes];
 #pragma unroll
     for (int t = 0; t < kMaxTypes; ++t) c[t] = 0;
+#pragma unroll 4
     for (long i0 = a0; i0 < a1; i0 += 64) {
         const long i = i0 + lane;
         const int ty = i < a1 ? types[i] : -1;
@@ -668,6 +669,7 @@ k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ 
 #pragma unroll
     for (int t = 0; t < kMaxTypes; ++t) run[t] = t < T ? base_s[wave][t] : 0;
     const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll 4
     for (long i0 = a0; i0 < a1; i0 += 64) {
         const long i = i0 + lane;
         const int ty = i < a1 ? types[i] : -1;
