@@ -13,7 +13,10 @@ teacher-model targets.
 
 Prints one JSON line (rank 0) with the throughput in structures/s, the
 roofline position of the dominant kernel, the plain-PyTorch autograd
-double-backward comparator on the same GPU, and the FP64 CPU oracle baseline.
+double-backward comparator on the same GPU, and the FP64 CPU oracle baseline;
+beside them, outside the timed steps, the neighbour build (first and warm)
+and the forward-only path (E, F, W per call, and with the lists rebuilt before
+every call as in a molecular-dynamics loop).
 """
 
 from __future__ import annotations
@@ -376,6 +379,31 @@ def main():
                      "avg_launch_us": round(avg_ms * 1e3, 2)})
     kernel_table = {r[0]: round(r[2] * 1e3, 2) for r in rows}
 
+    # forward-only path (inference, MD): E, F, W per call on the resident lists,
+    # and with the lists rebuilt before every call as an MD step would
+    fb, fnb = (tune_b, tune_nb) if epoch_mode else (gb, nb)
+    fws, nbws, reps = N.workspace(model, fb, fnb), N.workspace(model, fb), 20
+    for _ in range(2):
+        N.nep_forward(model, th, qs, fb, fnb, fws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        N.nep_forward(model, th, qs, fb, fnb, fws)
+    b.record()
+    torch.cuda.synchronize()
+    fwd_ms = a.elapsed_time(b) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nb_md = N.nep_build_neighbors(model, fb, capacity=fnb.num_pairs, ws=nbws)
+        N.nep_forward(model, th, qs, fb, nb_md, fws)
+    torch.cuda.synchronize()
+    md_ms = (time.perf_counter() - t0) * 1e3 / reps
+    del nb_md, fws, nbws
+    forward = {"ms_per_call": round(fwd_ms, 4), "structures_per_s": round(fb.num_structures / (fwd_ms * 1e-3), 1),
+               "ms_per_call_with_neighbor_rebuild": round(md_ms, 3)}
+    log(f"forward only: {fwd_ms:.4f} ms per call, {md_ms:.3f} ms with the neighbour lists rebuilt")
+
     # comparator: plain PyTorch autograd double backward on the same GPU
     comp = None
     if not args.no_comparator:
@@ -462,6 +490,7 @@ def main():
         "kernels_avg_us": kernel_table,
         "neighbor_build_ms": round(nbr_ms, 2),
         "neighbor_build_first_ms": round(nbr_first_ms, 2),
+        "forward_only": forward,
     }
     print(json.dumps(out), flush=True)
     if args.json_out:
