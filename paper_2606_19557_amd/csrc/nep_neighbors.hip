@@ -167,6 +167,13 @@ k_bin_atoms(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
     atomicAdd(bin_count + gb + 1, 1ull);
 }
 
+// bad != 0 after the launch if a species lies outside [0, T).
+__global__ void __launch_bounds__(kNbBlock)
+k_check_types(long Na, int T, const int* __restrict__ types, unsigned int* __restrict__ bad) {
+    const long i = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (i < Na && (types[i] < 0 || types[i] >= T)) atomicOr(bad, 1u);
+}
+
 // Scatter atoms into their bins (arbitrary order within a bin, fixed below).
 __global__ void __launch_bounds__(kNbBlock)
 k_bin_fill(long Na, const int* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
@@ -216,7 +223,7 @@ constexpr int kNbTeam = 16;
 
 template <typename R, bool FILL, int MT>
 __global__ void __launch_bounds__(kNbBlock)
-k_neighbors(long Na, int T, const int* __restrict__ types, const double* __restrict__ cells, double rcR,
+k_neighbors(long Na, int T, const double* __restrict__ cells, double rcR,
             double rcA, const int* __restrict__ atom_struct, const int* __restrict__ atom_bin,
             const double* __restrict__ wpos, const int* __restrict__ sbins, const int64_t* __restrict__ bin_base,
             const int64_t* __restrict__ bin_start, const BinRec* __restrict__ bin_rec, int* __restrict__ seg,
@@ -393,6 +400,7 @@ k_reverse(long Na, long npairs, int T, const int* __restrict__ types, const int*
     const long j = rec_j(a);
     if (j < i) return;  // searched from the other end
     const int ti = types[i];
+    if (ti < 0 || ti >= T) return;  // reported by k_check_types
     int64_t g0 = row[j];
     for (int b = 0; b < ti; ++b) g0 += seg[(j * T + b) * 2];
     const int n = seg[(j * T + ti) * 2];
@@ -915,26 +923,29 @@ template <typename R>
 nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors* nb, void* ws, size_t ws_bytes) {
     const long Na = b->num_atoms;
     const int Ns = b->num_structures, T = c.dm.T;
-    if (ws_bytes < sizeof(int64_t) * 2) return fail(NEP_ERR_WORKSPACE, "workspace too small for neighbour totals");
+    if (ws_bytes < sizeof(int64_t) * 3) return fail(NEP_ERR_WORKSPACE, "workspace too small for neighbour totals");
     int64_t* totals = static_cast<int64_t*>(ws);
     hipStream_t st = c.stream;
     const R* pos = static_cast<const R*>(b->positions);
     const int grid = int((Na + kNbBlock - 1) / kNbBlock);
     const int team_grid = int((Na + kNbBlock / kNbTeam - 1) / (kNbBlock / kNbTeam));
-    // Host-side validation of the index arrays every later kernel trusts:
-    // offsets must run 0 .. Na without decreasing and species must lie in [0, T).
+    // The offsets, which size the bins below, are checked on the host: they
+    // must run 0 .. Na without decreasing. Species are checked on the device
+    // (totals[2] flags one outside [0, T), read back with the pair count); every
+    // kernel below stays inside its arrays whatever the species, and the call
+    // fails before the lists are filled.
     {
         std::vector<int64_t> off(static_cast<size_t>(Ns) + 1);
         NEP_HIP(hipMemcpyAsync(off.data(), b->atom_offset, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost, st));
-        std::vector<int> typ(static_cast<size_t>(Na));
-        if (Na > 0) NEP_HIP(hipMemcpyAsync(typ.data(), b->types, sizeof(int) * typ.size(), hipMemcpyDeviceToHost, st));
         NEP_HIP(hipStreamSynchronize(st));
         if (off[0] != 0 || off[Ns] != Na) return fail(NEP_ERR_INVALID_ARG, "atom_offset must run from 0 to num_atoms");
         for (int s = 0; s < Ns; ++s)
             if (off[s + 1] < off[s]) return fail(NEP_ERR_INVALID_ARG, "atom_offset decreases at structure %d", s);
-        for (long i = 0; i < Na; ++i)
-            if (typ[i] < 0 || typ[i] >= T) return fail(NEP_ERR_INVALID_ARG, "atom %ld has species %d outside [0, %d)", i, typ[i], T);
     }
+    NEP_LAUNCH("neighbors_check", k_zero<int64_t>, dim3(1), dim3(kNbBlock), 0, st, 3L, totals);
+    if (Na > 0)
+        NEP_LAUNCH("neighbors_check", k_check_types, dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+                   reinterpret_cast<unsigned int*>(totals + 2));
     // cell-list scratch in the workspace after the totals
     const long max_bins = Na + Ns;
     size_t o = 64;
@@ -973,7 +984,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                    (const double*)wpos, b->types, bin_rec);
         nep_status e2 = with_max_types(T, [&](auto mt) -> nep_status {
             NEP_LAUNCH("neighbors_count", (k_neighbors<R, false, decltype(mt)::value>), dim3(team_grid),
-                       dim3(kNbBlock), 0, st, Na, T, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct,
+                       dim3(kNbBlock), 0, st, Na, T, b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct,
                        atom_bin, wpos, sbins, bin_base, bin_start, bin_rec, nb->seg_count, nb->row_offset,
                        (Rec<R>*)nullptr);
             return NEP_OK;
@@ -985,9 +996,9 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
                    nb->seg_count, totals);
     } else {
         // row offsets over many blocks; totals[0] = pairs (the last offset),
-        // totals[1] = angular pairs (block sums added atomically, in integers)
+        // totals[1] = angular pairs (block sums added atomically, in integers,
+        // onto the zero written before the species check)
         const long ntiles = (Na + kTile - 1) / kTile;
-        NEP_LAUNCH("neighbors_scan", k_zero<int64_t>, dim3(1), dim3(kNbBlock), 0, st, 2L, totals);
         NEP_LAUNCH("neighbors_scan", k_tile_sums, dim3(int(ntiles)), dim3(kTileThreads), 0, st, Na,
                    (const int64_t*)nb->row_offset, tile, T, (const int*)nb->seg_count,
                    reinterpret_cast<unsigned long long*>(totals + 1));
@@ -999,9 +1010,10 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
         nep_status e = species_sort(Na, T, b->types, nb->species_order, nb->species_offset, sort_cnt, st);
         if (e) return e;
     }
-    int64_t host_tot[2] = {0, 0};
+    int64_t host_tot[3] = {0, 0, 0};
     NEP_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, st));
     NEP_HIP(hipStreamSynchronize(st));
+    if (host_tot[2] != 0) return fail(NEP_ERR_INVALID_ARG, "an atom's species lies outside [0, %d)", T);
     nb->num_pairs = host_tot[0];
     nb->num_angular_pairs = host_tot[1];
     if (host_tot[0] >= (int64_t(1) << 31)) return fail(NEP_ERR_UNSUPPORTED, "more than 2^31-1 pairs in one batch");
@@ -1012,7 +1024,7 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     if (Na > 0 && host_tot[0] > 0) {
         nep_status e2 = with_max_types(T, [&](auto mt) -> nep_status {
             NEP_LAUNCH("neighbors_fill", (k_neighbors<R, true, decltype(mt)::value>), dim3(team_grid),
-                       dim3(kNbBlock), 0, st, Na, T, b->types, b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct,
+                       dim3(kNbBlock), 0, st, Na, T, b->cells, c.dm.rcR, c.dm.rcA, nb->atom_struct,
                        atom_bin, wpos, sbins, bin_base, bin_start, bin_rec, nb->seg_count, nb->row_offset,
                        static_cast<Rec<R>*>(nb->pairs));
             return NEP_OK;

@@ -31,7 +31,7 @@ constexpr double kScrD[4] = {3.19980, 0.94229, 0.40290, 0.20162};
 struct ZblArgs {
     double z[kMaxTypes];   // nuclear charge of each species
     double zp[kMaxTypes];  // Z^0.23 / (0.8854 a_0): inverse screening length = zp_i + zp_j
-    double r_in, r_out2, width, pi_over_width;
+    double r_in, r_out2, pi_over_width;
 };
 
 // phi(r) and phi'(r) of one pair (switch included).
@@ -193,8 +193,7 @@ nep_status zbl_add(const Dims& dm, bool f64, const nep_zbl* z, const nep_batch* 
     }
     a.r_in = z->r_inner;
     a.r_out2 = z->r_outer * z->r_outer;
-    a.width = z->r_outer - z->r_inner;
-    a.pi_over_width = M_PI / a.width;
+    a.pi_over_width = M_PI / (z->r_outer - z->r_inner);
     const long Na = long(b->num_atoms);
     return f64 ? launch_zbl<double>(a, dm.T, b->num_structures, Na, b->atom_offset, b->types, nb->row_offset,
                                     nb->seg_count, nb->pairs, scale, energy, force, virial, ws, st)

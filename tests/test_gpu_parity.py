@@ -300,3 +300,23 @@ def test_fused_plan_parity(name, idx, dtype, plan):
     gv = N.nep_backward(model, theta, qs, gb, nb, torch.tensor(dE, device="cuda"),
                         torch.tensor(dF, device="cuda"), torch.tensor(dW, device="cuda"), ws)
     assert rel_err(gv.double().cpu().numpy(), O.vjp(m, th, s, b, dE, dF, dW)) < tol["G"]
+
+
+@pytest.mark.parametrize("bad", [3, -1])
+def test_build_rejects_species_out_of_range(bad):
+    """A species outside [0, T) is found on the device and reported with the
+    pair count; the lists of a valid batch built afterwards are unaffected."""
+    _say(f"neighbors species {bad}")
+    from dataclasses import replace
+
+    md, m, b, th, s, tg = fixture(SMALL_ALLOY, seed=7, batch=small_alloy_batch())
+    model = N.Model.from_dict(md, dtype="f32")
+    typ = np.array(b.types, copy=True)
+    typ[len(typ) // 2] = bad
+    with pytest.raises(N.NepError) as e:
+        N.nep_build_neighbors(model, N.Batch.from_host(replace(b, types=typ)))
+    assert e.value.code == N.nep.NEP_ERR_INVALID_ARG and "species" in str(e.value)
+    ok = N.nep_build_neighbors(model, N.Batch.from_host(b))
+    ref = N.nep_build_neighbors(model, N.Batch.from_host(b))
+    assert ok.num_pairs == ref.num_pairs > 0
+    assert torch.equal(ok.row_offset, ref.row_offset) and torch.equal(ok.reverse[:ok.num_pairs], ref.reverse[:ref.num_pairs])
