@@ -245,9 +245,22 @@ k_neighbors(long Na, int T, const double* __restrict__ cells, double rcR,
         c[1] = loc % nb[1];
         c[0] = loc / nb[1];
     }
-    int kk[3];
-    for (int d = 0; d < 3; ++d) kk[d] = int(ceil(rcR * nb[d] / ci.w[d] + 1e-9));
     const double ri[3] = {wpos[3 * i], wpos[3 * i + 1], wpos[3 * i + 2]};
+    // Bin t along direction d is the slab t/n_d <= f_d < (t+1)/n_d between two
+    // lattice planes; an atom at fractional coordinate f is at least
+    // w_d * (distance in f) from every point of it. Slabs that far or farther
+    // (with a 1e-9 A margin) are dropped from both ends of the range the
+    // bins c +- kk would cover, per direction.
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        const int kk = int(ceil(rcR * nb[d] / ci.w[d] + 1e-9));
+        const double f = ri[0] * ci.Hi[d] + ri[1] * ci.Hi[3 + d] + ri[2] * ci.Hi[6 + d];
+        const double rcut = rcR + 1e-9;
+        lo[d] = c[d] - kk;
+        hi[d] = c[d] + kk;
+        while (lo[d] < c[d] && ci.w[d] * (f - double(lo[d] + 1) / nb[d]) >= rcut) ++lo[d];
+        while (hi[d] > c[d] && ci.w[d] * (double(hi[d]) / nb[d] - f) >= rcut) --hi[d];
+    }
     const double rc2R = rcR * rcR, rc2A = rcA * rcA;
     // per species {angular, radial-only}: FILL write cursors, COUNT {all, angular} counts
     int cur[2 * MT];
@@ -265,12 +278,12 @@ k_neighbors(long Na, int T, const double* __restrict__ cells, double rcR,
             acc += seg[(i * T + b) * 2];
         }
     }
-    for (int d0 = -kk[0]; d0 <= kk[0]; ++d0) {
-        const int t0 = c[0] + d0, m0 = floordiv(t0, nb[0]), b0 = t0 - m0 * nb[0];
-        for (int d1 = -kk[1]; d1 <= kk[1]; ++d1) {
-            const int t1 = c[1] + d1, m1 = floordiv(t1, nb[1]), b1 = t1 - m1 * nb[1];
-            for (int d2 = -kk[2]; d2 <= kk[2]; ++d2) {
-                const int t2 = c[2] + d2, m2 = floordiv(t2, nb[2]), b2 = t2 - m2 * nb[2];
+    for (int t0 = lo[0]; t0 <= hi[0]; ++t0) {
+        const int m0 = floordiv(t0, nb[0]), b0 = t0 - m0 * nb[0];
+        for (int t1 = lo[1]; t1 <= hi[1]; ++t1) {
+            const int m1 = floordiv(t1, nb[1]), b1 = t1 - m1 * nb[1];
+            for (int t2 = lo[2]; t2 <= hi[2]; ++t2) {
+                const int m2 = floordiv(t2, nb[2]), b2 = t2 - m2 * nb[2];
                 double sh[3];
                 for (int x = 0; x < 3; ++x) sh[x] = m0 * ci.H[x] + m1 * ci.H[3 + x] + m2 * ci.H[6 + x] - ri[x];
                 const bool self_image = m0 == 0 && m1 == 0 && m2 == 0;
