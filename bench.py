@@ -1,7 +1,8 @@
 """Benchmark of the NEP training step on one MI355X.
 
 One step = nep_loss_and_grad (descriptors, network, forces, virials, loss,
-analytic parameter gradient) + nep_adam_step over the whole batch, with the
+analytic parameter gradient) + nep_adam_step over the whole batch (as the one
+call nep_train_step, which takes the update in the gradient's last kernel), with the
 batch and its neighbour lists already resident in HBM (the lists are built
 once per dataset and timed separately, as the paper caches them).
 
@@ -312,9 +313,10 @@ def main():
             b_, nb_, tg_ = data.minibatch(mbs[k], ids_device=mbs_dev[k])
         else:
             b_, nb_, tg_ = gb, nb, targets
-        N.nep_loss_and_grad(model, th, qs, b_, nb_, tg_, ws, grad=grad, loss=loss)
         step_no[0] += 1
-        N.nep_adam_step(th, grad, m_, v_, vm_, step_no[0], adam)
+        # nep_loss_and_grad + nep_adam_step, the update taken in the kernel that
+        # finishes the gradient
+        N.nep_train_step(model, th, qs, b_, nb_, tg_, m_, v_, vm_, step_no[0], adam, ws, grad=grad, loss=loss)
 
     for _ in range(args.warmup):
         step()

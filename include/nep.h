@@ -266,6 +266,18 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
 nep_status nep_adam_step(int64_t num_params, int32_t dtype, void* theta, const void* grad, void* m, void* v,
                          void* vmax, int64_t t, const nep_adam_cfg* cfg, void* stream);
 
+/* One training step: nep_loss_and_grad followed by nep_adam_step on the same
+ * stream, with the Adam/AMSGrad update (Eqs. 8-13, step t, 1-based) taken in
+ * the kernel that finishes the gradient, one launch fewer than the two calls.
+ * theta [P] is read by the whole pass and updated in place at its end; m, v,
+ * vmax [P] as in nep_adam_step; loss [4] and grad [P] as in nep_loss_and_grad
+ * (grad holds the gradient at the old theta). Results are bitwise those of the
+ * two calls. Errors as in either call; nothing is launched on an error. */
+nep_status nep_train_step(const nep_model* model, void* theta, const void* q_scale, const nep_batch* batch,
+                          const nep_neighbors* nbr, const nep_targets* targets, void* m, void* v, void* vmax,
+                          int64_t t, const nep_adam_cfg* cfg, double* loss, void* grad, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* Eq. (2) factors from descriptors: q_scale[nu] = 1/(max_i q[i][nu] - min_i q[i][nu]),
  * or 1 where that range is below 1e-10. descriptor [Na][D], q_scale [D], dtype. */
 nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int32_t dtype, const void* descriptor,

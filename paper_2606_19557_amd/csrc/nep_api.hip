@@ -289,6 +289,26 @@ static nep_status base_ctx(const nep_model* model, const void* theta, const void
 
 static nep_status dispatch(const Ctx& c, const ShapeEntry* se) { return c.f64 ? se->f64(c) : se->f32(c); }
 
+static AdamArgs adam_args(const nep_adam_cfg* cfg, int64_t t) {
+    AdamArgs a;
+    a.lr = cfg->lr;
+    a.b1 = cfg->beta1;
+    a.b2 = cfg->beta2;
+    a.eps = cfg->eps;
+    a.bc1 = 1.0 - std::pow(cfg->beta1, double(t));
+    a.bc2 = 1.0 - std::pow(cfg->beta2, double(t));
+    a.amsgrad = cfg->amsgrad;
+    a.mode = cfg->amsgrad_mode;
+    return a;
+}
+
+static nep_status check_adam(const nep_adam_cfg* cfg, int64_t t) {
+    if (t < 1 || !cfg) return fail(NEP_ERR_INVALID_ARG, "bad Adam arguments (t %lld, cfg %p)", (long long)t, (const void*)cfg);
+    if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0 && cfg->beta2 >= 0.0 && cfg->beta2 < 1.0 && cfg->eps >= 0.0))
+        return fail(NEP_ERR_INVALID_ARG, "Adam constants out of range");
+    return NEP_OK;
+}
+
 }  // namespace nep
 
 using namespace nep;
@@ -472,21 +492,52 @@ nep_status nep_adam_step(int64_t num_params, int32_t dtype, void* theta, const v
     if (!theta || !grad || !m || !v || (cfg->amsgrad && !vmax)) return fail(NEP_ERR_INVALID_ARG, "NULL Adam array");
     if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0 && cfg->beta2 >= 0.0 && cfg->beta2 < 1.0 && cfg->eps >= 0.0))
         return fail(NEP_ERR_INVALID_ARG, "Adam constants out of range");
-    const double bc1 = 1.0 - std::pow(cfg->beta1, double(t)), bc2 = 1.0 - std::pow(cfg->beta2, double(t));
+    const AdamArgs a = adam_args(cfg, t);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int grid = int((num_params + kRedBlock - 1) / kRedBlock);
     if (dtype == NEP_F64) {
         NEP_LAUNCH("adam", (k_adam<double>), dim3(grid), dim3(kRedBlock), 0, st, long(num_params),
                    static_cast<double*>(theta), static_cast<const double*>(grad), static_cast<double*>(m),
-                   static_cast<double*>(v), static_cast<double*>(vmax), cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, bc1,
-                   bc2, cfg->amsgrad, cfg->amsgrad_mode);
+                   static_cast<double*>(v), static_cast<double*>(vmax), a);
     } else {
         NEP_LAUNCH("adam", (k_adam<float>), dim3(grid), dim3(kRedBlock), 0, st, long(num_params),
                    static_cast<float*>(theta), static_cast<const float*>(grad), static_cast<float*>(m),
-                   static_cast<float*>(v), static_cast<float*>(vmax), cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, bc1,
-                   bc2, cfg->amsgrad, cfg->amsgrad_mode);
+                   static_cast<float*>(v), static_cast<float*>(vmax), a);
     }
     return NEP_OK;
+}
+
+nep_status nep_train_step(const nep_model* model, void* theta, const void* q_scale, const nep_batch* batch,
+                          const nep_neighbors* nbr, const nep_targets* tg, void* m, void* v, void* vmax, int64_t t,
+                          const nep_adam_cfg* cfg, double* loss, void* grad, void* ws, size_t ws_bytes, void* stream) {
+    Ctx c;
+    const ShapeEntry* se = nullptr;
+    nep_status s = base_ctx(model, theta, q_scale, batch, nbr, ws, ws_bytes, stream, Mode::LossGrad, &c, &se);
+    if (s) return s;
+    if (!tg || !loss || !grad) return fail(NEP_ERR_INVALID_ARG, "targets, loss or grad is NULL");
+    if (batch->num_structures > 0 && (!tg->energy || !tg->virial))
+        return fail(NEP_ERR_INVALID_ARG, "target energy/virial is NULL");
+    if (batch->num_atoms > 0 && !tg->force) return fail(NEP_ERR_INVALID_ARG, "target force is NULL");
+    if (!std::isfinite(tg->lambda_e) || !std::isfinite(tg->lambda_f) || !std::isfinite(tg->lambda_v))
+        return fail(NEP_ERR_INVALID_ARG, "loss weights must be finite");
+    if ((s = check_adam(cfg, t))) return s;
+    if (!m || !v || (cfg->amsgrad && !vmax)) return fail(NEP_ERR_INVALID_ARG, "NULL Adam array");
+    c.Et = tg->energy;
+    c.Ft = tg->force;
+    c.Wt = tg->virial;
+    c.has_v = tg->has_virial;
+    c.lam_e = tg->lambda_e;
+    c.lam_f = tg->lambda_f;
+    c.lam_v = tg->lambda_v;
+    c.loss = loss;
+    c.grad = grad;
+    c.adam = 1;
+    c.adam_args = adam_args(cfg, t);
+    c.theta_out = theta;
+    c.m = m;
+    c.v = v;
+    c.vmax = vmax;
+    return dispatch(c, se);
 }
 
 nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int32_t dtype, const void* descriptor,

@@ -318,6 +318,14 @@ __device__ __forceinline__ void q4_hess_vec(const R* a, const R* da, R* out) {
 // that every XCD walks one contiguous range of tiles (a bijection on
 // [0, nb)): neighbouring atoms, and the pair slots they write for each other,
 // then share an L2.
+// Constants of one Adam/AMSGrad step t (Eqs. 8-13): bc1 = 1 - beta1^t and
+// bc2 = 1 - beta2^t are the bias corrections; mode 0 keeps the running maximum
+// of the bias-corrected second moment, mode 1 that of the raw one.
+struct AdamArgs {
+    double lr, b1, b2, eps, bc1, bc2;
+    int amsgrad, mode;
+};
+
 constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int per = nb / kXcds, rem = nb % kXcds, x = b % kXcds, k = b / kXcds;

@@ -96,6 +96,13 @@ struct Ctx {
     // outputs
     double* loss;
     void* grad;
+    // fused Adam/AMSGrad step after the gradient (nep_train_step)
+    int adam;
+    AdamArgs adam_args;
+    void* theta_out;
+    void* m;
+    void* v;
+    void* vmax;
     double* E_out;
     void* F_out;
     double* W_out;

@@ -165,7 +165,8 @@ nep_status run_shape(const Ctx& c) {
                    st, dm, Sh::NR * Sh::KR, Wd(L.outer_part), L.outer_rows, Wd(L.ang_part), L.ang_rows, Wd(L.stage));
     NEP_LAUNCH("final_reduce", (k_final_reduce<R>), dim3(int((dm.offB1 + kRedBlock) / kRedBlock)), dim3(kRedBlock), 0,
                st, dm, c.Ns, c.atom_offset, Wd(L.stage), Na > 0 ? kStageGroups : 0, Wd(L.ebar), Wd(L.lossp), c.lam_e,
-               c.lam_f, c.lam_v, static_cast<R*>(c.grad), loss ? c.loss : nullptr);
+               c.lam_f, c.lam_v, static_cast<R*>(c.grad), loss ? c.loss : nullptr, c.adam, c.adam_args,
+               static_cast<R*>(c.theta_out), static_cast<R*>(c.m), static_cast<R*>(c.v), static_cast<R*>(c.vmax));
     return NEP_OK;
 }
 

@@ -177,18 +177,22 @@ k_reduce_stage(Dims dm, int NRKR, const double* __restrict__ outer_part, int out
 }
 
 // Stage 2: grad[p] = sum over groups in order; b1 gets -sum_s N_a^s ebar_s;
-// block 0 also writes loss[4] = {L, Delta_E, Delta_F, Delta_V}.
+// block 0 also writes loss[4] = {L, Delta_E, Delta_F, Delta_V}. With `adam`
+// set, the lane that finishes a parameter's gradient then takes its Adam step
+// (theta, m, v, vmax in place), as k_adam would after this kernel.
 template <typename R>
 __global__ void __launch_bounds__(kRedBlock)
 k_final_reduce(Dims dm, int Ns, const int64_t* __restrict__ off, const double* __restrict__ stage, int G,
                const double* __restrict__ ebar, const double* __restrict__ lossp, double lam_e, double lam_f,
-               double lam_v, R* __restrict__ grad, double* __restrict__ loss) {
+               double lam_v, R* __restrict__ grad, double* __restrict__ loss, int adam, AdamArgs aa,
+               R* __restrict__ theta, R* __restrict__ m, R* __restrict__ v, R* __restrict__ vmax) {
     const long p = (long)blockIdx.x * kRedBlock + threadIdx.x;
     if (p < dm.offB1) {
         double t = 0.0;
 #pragma unroll 8
         for (int g = 0; g < G; ++g) t += stage[(long)g * dm.offB1 + p];
         grad[p] = R(t);
+        if (adam) adam_update<R>(p, R(t), aa, theta, m, v, vmax);
     }
     if (blockIdx.x != 0) return;
     // -sum_s N_a^s ebar_s and the three loss parts: wave sums, one barrier,
@@ -223,6 +227,7 @@ k_final_reduce(Dims dm, int Ns, const int64_t* __restrict__ off, const double* _
         res[c] = t;
     }
     grad[dm.offB1] = R(res[0]);
+    if (adam) adam_update<R>(dm.offB1, R(res[0]), aa, theta, m, v, vmax);
     if (!loss) return;
     loss[0] = lam_e * res[1] + lam_f * res[2] + lam_v * res[3];
     loss[1] = res[1];
@@ -230,33 +235,38 @@ k_final_reduce(Dims dm, int Ns, const int64_t* __restrict__ off, const double* _
     loss[3] = res[3];
 }
 
-// One Adam/AMSGrad step (Eqs. 8-13), elementwise.
+// One Adam/AMSGrad step (Eqs. 8-13) of parameter p with gradient gp.
 template <typename R>
-__global__ void __launch_bounds__(kRedBlock)
-k_adam(long P, R* __restrict__ theta, const R* __restrict__ g, R* __restrict__ m, R* __restrict__ v,
-       R* __restrict__ vmax, double lr, double b1, double b2, double eps, double bc1, double bc2, int amsgrad,
-       int mode) {
-    const long p = (long)blockIdx.x * kRedBlock + threadIdx.x;
-    if (p >= P) return;
-    const R gp = g[p];
-    const R mp = R(b1) * m[p] + R(1.0 - b1) * gp;
-    const R vp = R(b2) * v[p] + R(1.0 - b2) * gp * gp;
+__device__ __forceinline__ void adam_update(long p, R gp, const AdamArgs& a, R* __restrict__ theta,
+                                            R* __restrict__ m, R* __restrict__ v, R* __restrict__ vmax) {
+    const R mp = R(a.b1) * m[p] + R(1.0 - a.b1) * gp;
+    const R vp = R(a.b2) * v[p] + R(1.0 - a.b2) * gp * gp;
     m[p] = mp;
     v[p] = vp;
-    const R mhat = mp / R(bc1);
+    const R mhat = mp / R(a.bc1);
     R denom;
-    if (!amsgrad) {
-        denom = sqrt(vp / R(bc2)) + R(eps);
-    } else if (mode == 0) {
-        const R vm = fmax(vmax[p], vp / R(bc2));
+    if (!a.amsgrad) {
+        denom = sqrt(vp / R(a.bc2)) + R(a.eps);
+    } else if (a.mode == 0) {
+        const R vm = fmax(vmax[p], vp / R(a.bc2));
         vmax[p] = vm;
-        denom = sqrt(vm) + R(eps);
+        denom = sqrt(vm) + R(a.eps);
     } else {
         const R vm = fmax(vmax[p], vp);
         vmax[p] = vm;
-        denom = sqrt(vm) / sqrt(R(bc2)) + R(eps);
+        denom = sqrt(vm) / sqrt(R(a.bc2)) + R(a.eps);
     }
-    theta[p] -= R(lr) * mhat / denom;
+    theta[p] -= R(a.lr) * mhat / denom;
+}
+
+// The step over all parameters, one lane each.
+template <typename R>
+__global__ void __launch_bounds__(kRedBlock)
+k_adam(long P, R* __restrict__ theta, const R* __restrict__ g, R* __restrict__ m, R* __restrict__ v,
+       R* __restrict__ vmax, AdamArgs a) {
+    const long p = (long)blockIdx.x * kRedBlock + threadIdx.x;
+    if (p >= P) return;
+    adam_update<R>(p, g[p], a, theta, m, v, vmax);
 }
 
 // q_scale[d] = 1/(max - min) over atoms, 1 for ranges below 1e-10 (Eq. 2).

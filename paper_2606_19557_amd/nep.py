@@ -22,7 +22,7 @@ NEP_F32, NEP_F64 = 0, 1
 
 EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_gather_batch", "nep_forward",
            "nep_loss_and_grad", "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale",
-           "nep_last_error", "nep_profile_enable", "nep_profile_read", "nep_zbl_add")
+           "nep_last_error", "nep_profile_enable", "nep_profile_read", "nep_zbl_add", "nep_train_step")
 
 
 class NepError(RuntimeError):
@@ -99,6 +99,9 @@ def lib():
         L.nep_autotune.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
                                    C.POINTER(c_targets), vp, vp, vp, C.c_size_t, i32, C.POINTER(c_plan), vp]
         L.nep_adam_step.argtypes = [i64, i32, vp, vp, vp, vp, vp, i64, C.POINTER(c_adam), vp]
+        L.nep_train_step.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
+                                     C.POINTER(c_targets), vp, vp, vp, i64, C.POINTER(c_adam), vp, vp, vp,
+                                     C.c_size_t, vp]
         L.nep_descriptor_scale.argtypes = [i64, i64, i32, vp, vp, vp]
         L.nep_zbl_add.argtypes = [C.POINTER(c_model), C.POINTER(c_zbl), C.POINTER(c_batch), C.POINTER(c_neighbors),
                                   C.c_double, vp, vp, vp, vp, C.c_size_t, vp]
@@ -480,6 +483,22 @@ def nep_adam_step(theta, grad, m, v, vmax, t: int, cfg: AdamConfig):
     c = cfg.c()
     _check(lib().nep_adam_step(theta.numel(), dt, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), _ptr(vmax), int(t),
                                C.byref(c), _stream()))
+
+
+def nep_train_step(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, targets: Targets, m, v, vmax,
+                   t: int, cfg: AdamConfig, ws=None, grad=None, loss=None):
+    """nep_loss_and_grad + nep_adam_step in one call (theta, m, v, vmax updated in
+    place); returns (loss[4] f64, grad [P]) with grad taken at the old theta."""
+    dev, dt = batch.positions.device, model.torch_dtype
+    P, _ = nep_param_count(model)
+    ws = ws if ws is not None else workspace(model, batch, nbr)
+    grad = grad if grad is not None else torch.empty(P, dtype=dt, device=dev)
+    loss = loss if loss is not None else torch.empty(4, dtype=torch.float64, device=dev)
+    mm, b, cn, tg, c = model.c(), batch.c(), nbr.c(), targets.c(), cfg.c()
+    _check(lib().nep_train_step(C.byref(mm), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), C.byref(tg),
+                                _ptr(m), _ptr(v), _ptr(vmax), int(t), C.byref(c), _ptr(loss), _ptr(grad), _ptr(ws),
+                                ws.numel(), _stream()))
+    return loss, grad
 
 
 def nep_profile_enable(on: bool):

@@ -15,8 +15,8 @@ from dataclasses import asdict, dataclass, field
 import numpy as np
 import torch
 
-from .nep import (AdamConfig, Batch, Model, Targets, Zbl, nep_adam_step, nep_build_neighbors, nep_gather_batch,
-                  nep_loss_and_grad, nep_param_count, nep_workspace_size, nep_zbl_add)
+from .nep import (AdamConfig, Batch, Model, Targets, Zbl, nep_build_neighbors, nep_gather_batch,
+                  nep_param_count, nep_train_step, nep_workspace_size, nep_zbl_add)
 
 
 class Dataset:
@@ -171,12 +171,13 @@ class Trainer:
         return np.random.Generator(np.random.PCG64(self.cfg.seed + 4000 + self.epoch)).permutation(n)
 
     def step(self, b, nb, tg):
-        """One optimisation step on a packed minibatch (loss stays on the device)."""
-        nep_loss_and_grad(self.model, self.theta, self.q_scale, b, nb, tg, self.ws, grad=self.grad, loss=self.loss)
+        """One optimisation step on a packed minibatch (loss stays on the device):
+        the loss gradient and the Adam update in one call (nep_train_step)."""
         self.t += 1
         a = self.cfg.adam
         cfg = AdamConfig(lr=self.sched.lr, beta1=a.beta1, beta2=a.beta2, eps=a.eps, amsgrad=a.amsgrad, mode=a.mode)
-        nep_adam_step(self.theta, self.grad, self.m, self.v, self.vmax, self.t, cfg)
+        nep_train_step(self.model, self.theta, self.q_scale, b, nb, tg, self.m, self.v, self.vmax, self.t, cfg,
+                       self.ws, grad=self.grad, loss=self.loss)
 
     def run_epoch(self, data: Dataset) -> np.ndarray:
         """One epoch; returns the epoch-averaged [L, Delta_E, Delta_F, Delta_V]."""

@@ -173,3 +173,24 @@ def test_zbl_validates_before_launching():
     assert call((26, 28), 1.0, 2.0, ws_bytes=319) == nep.NEP_ERR_WORKSPACE  # 80 bytes per atom
     rc = L.nep_zbl_add(C.byref(m), None, C.byref(batch), C.byref(nb), 1.0, vp, vp, vp, vp, 320, None)
     assert rc == nep.NEP_ERR_INVALID_ARG
+
+
+def test_train_step_validates_before_launching():
+    """The fused training step rejects a bad step index, Adam constants or NULL moments on the host."""
+    L = _lib_or_skip()
+    m = nep.Model(num_types=1, rc_r=6.0, rc_a=4.0, n_max_r=6, n_max_a=4, basis_r=8, basis_a=8, hidden=30).c()
+    batch = nep.c_batch(1, 4, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8))
+    nb = nep.c_neighbors(16, *([C.c_void_p(8)] * 7), 8, 4)
+    tg = nep.c_targets(C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None, 1.0, 1.0, 0.1)
+    vp = C.c_void_p(8)
+    cfg = nep.AdamConfig().c()
+
+    def call(t, mm=vp, c=cfg):
+        return L.nep_train_step(C.byref(m), vp, vp, C.byref(batch), C.byref(nb), C.byref(tg), mm, vp, vp, t,
+                                C.byref(c) if c is not None else None, vp, vp, vp, 1 << 30, None)
+
+    assert call(0) == nep.NEP_ERR_INVALID_ARG
+    assert call(1, mm=None) == nep.NEP_ERR_INVALID_ARG
+    assert call(1, c=None) == nep.NEP_ERR_INVALID_ARG
+    bad = nep.AdamConfig(beta1=1.0).c()
+    assert call(1, c=bad) == nep.NEP_ERR_INVALID_ARG and L.nep_last_error()

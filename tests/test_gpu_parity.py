@@ -320,3 +320,29 @@ def test_build_rejects_species_out_of_range(bad):
     ref = N.nep_build_neighbors(model, N.Batch.from_host(b))
     assert ok.num_pairs == ref.num_pairs > 0
     assert torch.equal(ok.row_offset, ref.row_offset) and torch.equal(ok.reverse[:ok.num_pairs], ref.reverse[:ref.num_pairs])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("amsgrad,mode", [(False, "paper"), (True, "paper"), (True, "torch")])
+def test_train_step_matches_loss_grad_then_adam(dtype, amsgrad, mode):
+    """nep_train_step is nep_loss_and_grad followed by nep_adam_step, bit for bit,
+    over three steps, under the plain and the fused launch plans."""
+    _say(f"train step {dtype} amsgrad={amsgrad} {mode}")
+    md, m, b, th, s, tg, model, gb, nb, ws, theta, qs = _setup("small_alloy", None, dtype)
+    targets = N.Targets(*tg, lambdas=(1.0, 1.0, 0.1), dtype=model.torch_dtype)
+    cfg = N.AdamConfig(lr=1e-2, amsgrad=amsgrad, mode=mode)
+    for plan in (None, N.Plan(8, 8, 8, 8, 2048, 64, 3)):
+        mdl = model.with_plan(plan)
+        w = N.workspace(mdl, gb, nb)
+        a = [theta.clone()] + [torch.zeros_like(theta) for _ in range(3)]
+        f = [theta.clone()] + [torch.zeros_like(theta) for _ in range(3)]
+        for t in (1, 2, 3):
+            la, ga = N.nep_loss_and_grad(mdl, a[0], qs, gb, nb, targets, w)
+            ga = ga.clone()
+            N.nep_adam_step(a[0], ga, a[1], a[2], a[3], t, cfg)
+            lf, gf = N.nep_train_step(mdl, f[0], qs, gb, nb, targets, f[1], f[2], f[3], t, cfg, w)
+            torch.cuda.synchronize()
+            assert torch.equal(la, lf) and torch.equal(ga, gf)
+            for x, y in zip(a, f):
+                assert torch.equal(x, y)
+        assert not torch.equal(a[0], theta)  # the parameters did move
