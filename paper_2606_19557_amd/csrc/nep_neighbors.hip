@@ -801,31 +801,29 @@ k_gather_atoms(long Na, int n, int T, const int* __restrict__ ids, const int64_t
     dst_row[a + 1] = pair_base[k] + (src_row[sa + 1] - src_row[src_off[sid]]);
 }
 
-// Per minibatch pair p < min(P, pair_base[n]) inside the rows written above:
-// the record with j renumbered and the reverse index moved to the minibatch's
+// Per minibatch pair p < min(P, pair_base[n]): a structure's pairs form one
+// contiguous range in the dataset's lists and in the minibatch's, so the pair
+// is found by its structure k (pair_base[k] <= p < pair_base[k + 1]) and
+// copied with j renumbered and the reverse index moved to the minibatch's
 // pair numbering.
 template <typename R>
 __global__ void __launch_bounds__(kNbBlock)
-k_gather_pairs(long P, long Na, int n, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
+k_gather_pairs(long P, int n, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
                const int64_t* __restrict__ src_row, const Rec<R>* __restrict__ src_pairs,
                const int* __restrict__ src_rev, const int64_t* __restrict__ dst_off,
-               const int64_t* __restrict__ pair_base, const int* __restrict__ dst_struct,
-               const int64_t* __restrict__ dst_row, Rec<R>* __restrict__ dst_pairs, int* __restrict__ dst_rev) {
-    // rows 0 .. hi0-1 were written by k_gather_atoms (hi0 <= the caller's Na);
-    // pairs 0 .. lim-1 lie inside them
-    const long hi0 = Na < dst_off[n] ? Na : dst_off[n];
-    const long lim = hi0 == 0 ? 0 : min(min(P, (long)pair_base[n]), (long)dst_row[hi0]);
+               const int64_t* __restrict__ pair_base, Rec<R>* __restrict__ dst_pairs, int* __restrict__ dst_rev) {
+    const long lim = min(P, (long)pair_base[n]);
     const long p0 = (long)blockIdx.x * kNbBlock;
     if (p0 >= lim) return;  // the whole block
-    // the block's pairs lie in a short run of rows: two lanes bisect all rows for
-    // its first and last pair, every lane then bisects inside that run
-    __shared__ long run_s[2];
+    // the block's pairs lie in a short run of structures: two lanes bisect
+    // pair_base for its first and last pair, every lane then bisects inside it
+    __shared__ int run_s[2];
     if (threadIdx.x < 2) {
         const long key = threadIdx.x == 0 ? p0 : min(p0 + kNbBlock, lim) - 1;
-        long lo = 0, hi = hi0;
+        int lo = 0, hi = n;  // pair_base[lo] <= key < pair_base[hi]
         while (hi - lo > 1) {
-            const long mid = (lo + hi) >> 1;
-            if (dst_row[mid] <= key)
+            const int mid = (lo + hi) >> 1;
+            if (pair_base[mid] <= key)
                 lo = mid;
             else
                 hi = mid;
@@ -835,18 +833,17 @@ k_gather_pairs(long P, long Na, int n, const int* __restrict__ ids, const int64_
     __syncthreads();
     const long p = p0 + threadIdx.x;
     if (p >= lim) return;
-    long lo = run_s[0], hi = run_s[1] + 1;  // dst_row[lo] <= p < dst_row[hi]
+    int lo = run_s[0], hi = run_s[1] + 1;
     while (hi - lo > 1) {
-        const long mid = (lo + hi) >> 1;
-        if (dst_row[mid] <= p)
+        const int mid = (lo + hi) >> 1;
+        if (pair_base[mid] <= p)
             lo = mid;
         else
             hi = mid;
     }
-    const long a = lo;
-    const int k = dst_struct[a], sid = ids[k];
-    const long sa = src_off[sid] + (a - dst_off[k]);
-    const long sp = src_row[sa] + (p - dst_row[a]);
+    const int k = lo, sid = ids[k];
+    const long s0 = src_row[src_off[sid]];  // the structure's first pair in the dataset
+    const long sp = s0 + (p - pair_base[k]);
     Rec<R> r = src_pairs[sp];
     const long j = long(rec_j(r)) - src_off[sid] + dst_off[k];
     if constexpr (sizeof(R) == 4)
@@ -855,7 +852,7 @@ k_gather_pairs(long P, long Na, int n, const int* __restrict__ ids, const int64_
         r.w = __longlong_as_double((long long)j);
     dst_pairs[p] = r;
     const int rv = src_rev[sp];
-    dst_rev[p] = rv < 0 ? -1 : int(rv - src_row[src_off[sid]] + pair_base[k]);
+    dst_rev[p] = rv < 0 ? -1 : int(rv - s0 + pair_base[k]);
 }
 
 nep_status species_sort(long Na, int T, const int* types, int* order, int64_t* soff, int* cnt, hipStream_t st);
@@ -890,8 +887,8 @@ nep_status gather_impl(const Ctx& c, const nep_batch* src, const nep_neighbors* 
                    dn->atom_struct, dn->row_offset);
     if (P > 0)
         NEP_LAUNCH("gather_pairs", (k_gather_pairs<R>), dim3(int((P + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
-                   st, P, Na, n, ids, src->atom_offset, sn->row_offset, static_cast<const Rec<R>*>(sn->pairs), sn->reverse,
-                   dst_off, pair_base, dn->atom_struct, dn->row_offset, static_cast<Rec<R>*>(dn->pairs), dn->reverse);
+                   st, P, n, ids, src->atom_offset, sn->row_offset, static_cast<const Rec<R>*>(sn->pairs), sn->reverse,
+                   dst_off, pair_base, static_cast<Rec<R>*>(dn->pairs), dn->reverse);
     return species_sort(Na, T, dst_types, dn->species_order, dn->species_offset, nullptr, st);
 }
 
