@@ -658,14 +658,36 @@ k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ 
     int c[kMaxTypes];
 #pragma unroll
     for (int t = 0; t < kMaxTypes; ++t) c[t] = 0;
-#pragma unroll 4
-    for (long i0 = a0; i0 < a1; i0 += 64) {
-        const long i = i0 + lane;
-        const int ty = i < a1 ? types[i] : -1;
+    // up to REG steps per wave keep their species in registers for both
+    // passes (all loads in flight at once); longer slices reload them
+    constexpr int REG = 16;
+    const bool held = per <= REG * 64;  // the same for the whole block
+    int tr[REG];
+    if (held) {
 #pragma unroll
-        for (int t = 0; t < kMaxTypes; ++t) {
-            if (t >= T) break;
-            c[t] += __popcll(__ballot(ty == t));
+        for (int k = 0; k < REG; ++k) {
+            const long i = a0 + k * 64 + lane;
+            tr[k] = i < a1 ? types[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < REG; ++k) {
+            if (a0 + k * 64 >= a1) break;
+#pragma unroll
+            for (int t = 0; t < kMaxTypes; ++t) {
+                if (t >= T) break;
+                c[t] += __popcll(__ballot(tr[k] == t));
+            }
+        }
+    } else {
+#pragma unroll 4
+        for (long i0 = a0; i0 < a1; i0 += 64) {
+            const long i = i0 + lane;
+            const int ty = i < a1 ? types[i] : -1;
+#pragma unroll
+            for (int t = 0; t < kMaxTypes; ++t) {
+                if (t >= T) break;
+                c[t] += __popcll(__ballot(ty == t));
+            }
         }
     }
 #pragma unroll
@@ -690,6 +712,22 @@ k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ 
 #pragma unroll
     for (int t = 0; t < kMaxTypes; ++t) run[t] = t < T ? base_s[wave][t] : 0;
     const unsigned long long below = (1ull << lane) - 1ull;
+    if (held) {
+#pragma unroll
+        for (int k = 0; k < REG; ++k) {
+            if (a0 + k * 64 >= a1) break;
+            const long i = a0 + k * 64 + lane;
+            const int ty = tr[k];
+#pragma unroll
+            for (int t = 0; t < kMaxTypes; ++t) {
+                if (t >= T) break;
+                const unsigned long long m = __ballot(ty == t);
+                if (ty == t) order[run[t] + __popcll(m & below)] = (int)i;
+                run[t] += __popcll(m);
+            }
+        }
+        return;
+    }
 #pragma unroll 4
     for (long i0 = a0; i0 < a1; i0 += 64) {
         const long i = i0 + lane;
