@@ -93,3 +93,39 @@ def test_dataset_with_zbl_trains_nep_plus_zbl(dtype):
     tl, tg_ = (1e-9, 1e-9) if dtype == "f64" else (1e-5, 1e-4)
     assert rel_err(loss.cpu().numpy(), lo) < tl
     assert rel_err(g.double().cpu().numpy(), go) < tg_
+
+
+def test_zbl_self_images_and_empty_batch():
+    """A one-atom cell whose only ZBL partners are its own periodic images, a
+    two-atom cell and a bcc cell, FP64 against the oracle; an empty batch is a
+    no-op."""
+    print("zbl edge cases", flush=True)
+    from synth import structures as S
+
+    rng = np.random.default_rng(17)
+    structs = [
+        (np.diag([2.3, 2.6, 3.3]), np.array([[0.2, 0.1, 0.3]]), np.array([0], np.int32)),
+        (np.diag([2.9, 4.0, 3.2]), np.array([[0.1, 0.2, 0.3], [1.2, 1.4, 1.1]]), np.array([0, 0], np.int32)),
+        S.bcc_structure(rng, 15, a=3.2, sigma=0.15, exact_dims=(2, 2, 2)),
+    ]
+    b = S.pack(structs, 1)
+    md = dict(num_types=1, rc_r=5.0, rc_a=4.0, n_max_r=4, n_max_a=4, basis_r=8, basis_a=8, l_max=4, l_max_4b=0,
+              l_max_5b=0, hidden=30)
+    model = N.Model.from_dict(md, dtype="f64")
+    gb = N.Batch.from_host(b, dtype=torch.float64)
+    nb = N.nep_build_neighbors(model, gb)
+    z = N.Zbl((26,), 2.0, 3.0)
+    E = torch.zeros(3, dtype=torch.float64, device="cuda")
+    F = torch.zeros((b.num_atoms, 3), dtype=torch.float64, device="cuda")
+    W = torch.zeros((3, 9), dtype=torch.float64, device="cuda")
+    N.nep_zbl_add(model, z, gb, nb, E, F, W)
+    Ez, Fz, Wz = OZ.zbl((26,), 2.0, 3.0, b)
+    assert Ez[0] > 0 and np.abs(Fz[0]).max() < 1e-9 * Ez[0]  # a lone atom's images pull evenly
+    assert rel_err(E.cpu().numpy(), Ez) < 1e-10
+    assert np.abs(F.cpu().numpy() - Fz).max() < 1e-9 * max(1.0, np.abs(Fz).max())
+    assert rel_err(W.cpu().numpy(), Wz) < 1e-9
+    empty = N.Batch(np.zeros((0, 3)), np.zeros(0, np.int32), np.zeros((0, 3, 3)), np.zeros(1, np.int64),
+                    dtype=torch.float64)
+    enb = N.nep_build_neighbors(model, empty)
+    N.nep_zbl_add(model, z, empty, enb, None, None, None)
+    torch.cuda.synchronize()
