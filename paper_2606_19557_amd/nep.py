@@ -336,8 +336,9 @@ def nep_gather_batch(model: Model, src: Batch, src_nbr: Neighbors, src_targets, 
 
 
 def nep_forward(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, ws=None, want_force=True,
-                want_virial=True, want_descriptor=False):
-    """E [Ns] f64, F [Na,3], W [Ns,9] f64 (None when not asked) and optionally q [Na,D]."""
+                want_virial=True, want_descriptor=False, zbl=None):
+    """E [Ns] f64, F [Na,3], W [Ns,9] f64 (None when not asked) and optionally q [Na,D];
+    with `zbl` (a Zbl) the ZBL term is added to E, F and W (nep_zbl_add)."""
     dev, dt = batch.positions.device, model.torch_dtype
     P, D = nep_param_count(model)
     ws = ws if ws is not None else workspace(model, batch, nbr)
@@ -348,6 +349,8 @@ def nep_forward(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, ws=N
     m, b, cn = model.c(), batch.c(), nbr.c()
     _check(lib().nep_forward(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), _ptr(E), _ptr(F),
                              _ptr(W), _ptr(q), _ptr(ws), ws.numel(), _stream()))
+    if zbl is not None:
+        nep_zbl_add(model, zbl, batch, nbr, E, F, W, ws=ws)
     return (E, F, W, q) if want_descriptor else (E, F, W)
 
 

@@ -62,8 +62,7 @@ def test_zbl_outside_switch_is_zero_and_forward_sum():
     # NEP + ZBL predictions
     theta = torch.tensor(th, dtype=torch.float64, device="cuda")
     qs = torch.tensor(s, dtype=torch.float64, device="cuda")
-    E, F, W = N.nep_forward(model, theta, qs, gb, nb)
-    N.nep_zbl_add(model, N.Zbl(ZS, R_IN, R_OUT), gb, nb, E, F, W)
+    E, F, W = N.nep_forward(model, theta, qs, gb, nb, zbl=N.Zbl(ZS, R_IN, R_OUT))
     Eo, Fo, Wo = O.forward(m, th, s, b)
     Ez, Fz, Wz = OZ.zbl(ZS, R_IN, R_OUT, b)
     assert rel_err(E.cpu().numpy(), Eo + Ez) < 1e-9
