@@ -6,18 +6,21 @@ call nep_train_step, which takes the update in the gradient's last kernel), with
 batch and its neighbour lists already resident in HBM (the lists are built
 once per dataset and timed separately, as the paper caches them).
 
-Workload: 256 single-species periodic fcc cells with 32..256 atoms (noise
-0.15 A, strain up to 2%), radial/angular cutoff 6/4 A, n_max 6/4, basis 8/8,
-l_max 4, 30 hidden neurons, FP32 bulk arithmetic with FP64 per-structure and
-loss reductions; synthetic structures, random-initialised parameters and
-teacher-model targets.
+Default workload: the large-cell configuration, 32 periodic cells of
+4000-16000 atoms (277,380 atoms; half random 5-species alloys on an fcc
+lattice at 0.11 atoms/A^3, half dense liquids), radial/angular cutoff 6/5 A,
+n_max 10/8, basis 12/12, l_max 4, 100 hidden neurons, ~90 radial neighbours
+per atom; FP32 bulk arithmetic with FP64 per-structure and loss reductions;
+synthetic structures, random-initialised parameters and teacher-model
+targets. Other workloads: --workload.
 
 Prints one JSON line (rank 0) with the throughput in structures/s, the
-roofline position of the dominant kernel, the plain-PyTorch autograd
-double-backward comparator on the same GPU, and the FP64 CPU oracle baseline;
-beside them, outside the timed steps, the neighbour build (first and warm)
-and the forward-only path (E, F, W per call, and with the lists rebuilt before
-every call as in a molecular-dynamics loop).
+per-step spread, the roofline position of the dominant kernel and of the
+whole step, the plain-PyTorch autograd double-backward comparator on the same
+GPU, and the FP64 CPU oracle baseline; beside them, outside the timed steps,
+the neighbour build (first and warm) and the forward-only path (E, F, W per
+call, and with the lists rebuilt before every call as in a molecular-dynamics
+loop).
 """
 
 from __future__ import annotations
@@ -44,18 +47,18 @@ def parse():
     p.add_argument("--steps", type=int, default=None,
                    help="timed steps (default 50; a whole epoch of minibatches for a minibatch workload)")
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="fcc_uneven_256")
-    p.add_argument("--profile-steps", type=int, default=5)
+    p.add_argument("--workload", default="large5_32")
     p.add_argument("--comparator-steps", type=int, default=3)
     p.add_argument("--no-comparator", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-autotune", action="store_true", help="use the default launch plan")
     p.add_argument("--retune", action="store_true", help="tune the launch plan even when one is cached")
-    p.add_argument("--cpu-structures", type=int, default=256)
+    p.add_argument("--cpu-structures", type=int, default=0,
+                   help="oracle sample: the first N structures (default: 16 large cells, 64 alloy cells, else 256)")
     p.add_argument("--cpu-threads", type=int, default=0,
                    help="oracle threads for the CPU baseline (default: the host's cores, at most 16)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
-                   help="repeat the oracle over the sample until this much time has passed")
+                   help="repeat the all-thread oracle run over the sample until this much time has passed")
     p.add_argument("--json-out", default=None, help="also write the result line to this file")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also run one device-to-device copy of this many MiB (a known-size kernel that "
@@ -198,6 +201,81 @@ def measured_traffic(kernel, workload, plan=None):
     return val
 
 
+# --------------------------------------------------------------- CPU baseline
+
+
+def host_cpu():
+    """(logical CPUs, CPU model name) of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(args, w, host, th, qs, targets, log):
+    """The FP64 oracle's loss + gradient on a bounded sample of the workload:
+    one run on all threads (repeated up to --cpu-seconds) and one on a single
+    thread over the sample's first n/threads structures. The oracle's brute-force
+    neighbour search is timed by the oracle itself (thread-seconds) and left
+    out of the rates: single thread, wall minus search; all threads, wall
+    minus search thread-seconds over the threads in use."""
+    import oracle as O
+
+    default_n = {"large5_32": 16, "alloy4_1024": 64}.get(args.workload, 256)
+    n_s = min(args.cpu_structures or default_n, host.num_structures)
+    sub = host.subset(range(n_s))
+    om = O.Model(**w.model)
+    nproc, cpu_model = host_cpu()
+    threads = min(args.cpu_threads if args.cpu_threads > 0 else min(nproc, 16), n_s)
+    th_h = th.double().cpu().numpy()
+    qs_h = qs.double().cpu().numpy()
+    a0 = int(sub.atom_offset[-1])
+    Et_h = targets.energy[:n_s].cpu().numpy()
+    Ft_h = targets.force[:a0].double().cpu().numpy()
+    Wt_h = targets.virial[:n_s].cpu().numpy()
+    lam = w.lambdas
+
+    def run(batch, nthreads, seconds):
+        Et, Ft, Wt = Et_h[:batch.num_structures], Ft_h[:batch.num_atoms], Wt_h[:batch.num_structures]
+        O.search_seconds(reset=True)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.loss_and_grad(om, th_h, qs_h, batch, Et, Ft, Wt, lam, nthreads=nthreads)
+            reps += 1
+            wall = time.perf_counter() - t0
+            if wall >= seconds:
+                break
+        return reps, wall, O.search_seconds()
+
+    reps, wall, search = run(sub, threads, args.cpu_seconds)
+    compute = wall - search / threads
+    rate = reps * n_s / compute
+    one = sub.subset(range(max(1, n_s // threads)))
+    r1, wall1, search1 = run(one, 1, args.cpu_seconds / 4)
+    rate1 = r1 * one.num_structures / (wall1 - search1)
+    atoms = reps * a0 / compute
+    log(f"cpu oracle {rate:.3f} structures/s on {threads} threads ({reps} x {n_s} structures, {wall:.1f} s, "
+        f"search {search:.1f} thread-s excluded); 1 thread {rate1:.4f} structures/s; {nproc} CPUs: {cpu_model}")
+    return {"value": round(rate, 4), "unit": "structures/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_s} structures ({a0} atoms) of the workload x {reps}, FP64 loss + gradient; "
+                      f"the oracle's brute-force neighbour search excluded ({search:.1f} of "
+                      f"{wall * threads:.1f} thread-seconds); single-thread rate on the first "
+                      f"{one.num_structures} structures ({one.num_atoms} atoms) x {r1}",
+            "atoms_per_s": round(atoms, 1),
+            "value_with_search": round(reps * n_s / wall, 4),
+            "search_thread_s": round(search, 2),
+            "single_thread": {"value": round(rate1, 5), "unit": "structures/s",
+                              "atoms_per_s": round(one.num_atoms * r1 / (wall1 - search1), 1),
+                              "search_s": round(search1, 2), "wall_s": round(wall1, 2)},
+            "host": {"nproc": nproc, "cpu_model": cpu_model}}
+
+
 # ------------------------------------------------------------------- main
 
 
@@ -322,16 +400,25 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"warmup done, loss {loss[0].item():.6e}")
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # timed region: an event after every step (per-step spread) and, through
+    # nep_profile_enable, HIP events around every kernel launch on the launch
+    # stream (per-kernel durations over the same steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    N.nep_profile_enable(True)
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
+    evs[0].record()
+    for k in range(args.steps):
         step()
-    stop.record()
+        evs[k + 1].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    ms = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    prof = N.nep_profile_read()
+    N.nep_profile_enable(False)
     sps = structs_per_step / (ms * 1e-3)
-    log(f"timed {args.steps} steps: {ms:.4f} ms/step, {sps:.1f} structures/s, loss {loss[0].item():.6e}")
+    p10, p50, p90 = (float(np.percentile(per_step, q)) for q in (10, 50, 90))
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (median {p50:.4f}, p10 {p10:.4f}, p90 {p90:.4f}), "
+        f"{sps:.1f} structures/s, loss {loss[0].item():.6e}")
 
     if args.copy_calibration > 0:
         nbytes = args.copy_calibration << 20
@@ -343,29 +430,39 @@ def main():
         log(f"copy calibration: {nbytes} bytes read and written once")
         del src, dst
 
-    # per-kernel event timing on the launch stream
-    N.nep_profile_enable(True)
-    for _ in range(args.profile_steps):
-        step()
-    prof = N.nep_profile_read()
-    N.nep_profile_enable(False)
     rows = []
     for name, (n, tot) in prof.items():
         rows.append((name, n, tot / n))
         log(f"  kernel {name:22s} launches {n:4d}  avg {tot / n * 1e3:9.2f} us")
-    dom = max(rows, key=lambda r: r[2] * (r[1] / args.profile_steps))
-    name, n, avg_ms = dom
     used_plan = plan.as_dict() if plan is not None else dict(
         team_descriptor=8, team_force=8, team_tangent=8, team_coeff_grad=8, coeff_grad_blocks=2048, outer_chunk=64,
         network=1)
-    work = work_model(name, w.model, counts, fused=used_plan["network"] == 3)
+    fused = used_plan["network"] == 3
     peak_alu = PEAK_FP64_TFLOPS if w.dtype == "f64" else PEAK_FP32_TFLOPS
+    # whole step: algorithmic FLOPs and bytes of every kernel launched per step
+    step_fl = step_by = 0.0
+    for name, n, _ in rows:
+        wk = work_model(name, w.model, counts, fused=fused)
+        if wk is not None:
+            step_fl += wk[0] * n / args.steps
+            step_by += wk[1] * n / args.steps
+    step_roof = {"gflop": round(step_fl / 1e9, 3), "alg_mb": round(step_by / 1e6, 2),
+                 "flop_per_byte": round(step_fl / max(step_by, 1.0), 2),
+                 "alu_frac": round(step_fl / (ms * 1e-3) / 1e12 / peak_alu, 4),
+                 "hbm_frac": round(step_by / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    dom = max(rows, key=lambda r: r[2] * (r[1] / args.steps))
+    name, n, avg_ms = dom
+    work = work_model(name, w.model, counts, fused=fused)
     roof = None
     if work is not None:
         fl, by = work
         sec = avg_ms * 1e-3
-        t_alu, t_hbm = fl / (peak_alu * 1e12), by / (PEAK_HBM_GBS * 1e9)
         traffic = measured_traffic(name, args.workload, used_plan)
+        # the bound: FLOP time at the vector peak against the time to move the
+        # kernel's bytes at the HBM peak -- the measured HBM bytes when a
+        # counter summary of these sources exists, else the algorithmic bytes
+        t_alu = fl / (peak_alu * 1e12)
+        t_hbm = (traffic if traffic is not None else by) / (PEAK_HBM_GBS * 1e9)
         if t_alu >= t_hbm:
             achieved, peak = fl / sec / 1e12, peak_alu
             roof = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
@@ -377,8 +474,13 @@ def main():
         roof.update({"frac": round(achieved / peak, 4), "traffic": None if traffic is None else int(traffic),
                      "flops_per_launch": int(fl), "bytes_per_launch": int(by),
                      "alu_frac": round(fl / sec / 1e12 / peak_alu, 4),
+                     # the kernels are built without packed FP32 instructions:
+                     # the vector rate they can reach is half the published peak
+                     "alu_frac_nonpacked": round(fl / sec / 1e12 / (peak_alu / 2 if w.dtype == "f32" else peak_alu),
+                                                 4),
                      "hbm_frac": round(by / sec / 1e9 / PEAK_HBM_GBS, 4),
-                     "avg_launch_us": round(avg_ms * 1e3, 2)})
+                     "hbm_frac_measured": None if traffic is None else round(traffic / sec / 1e9 / PEAK_HBM_GBS, 4),
+                     "avg_launch_us": round(avg_ms * 1e3, 2), "step": step_roof})
     kernel_table = {r[0]: round(r[2] * 1e3, 2) for r in rows}
 
     # forward-only path (inference, MD): E, F, W per call on the resident lists,
@@ -439,33 +541,13 @@ def main():
             comp = {"kind": "torch autograd double backward", "error": repr(e)[:200]}
             log(f"comparator failed: {e!r}")
 
-    # CPU baseline: the FP64 oracle on the host cores
+    # CPU baseline: the FP64 oracle on the host cores, on the first structures
+    # of the workload, timed with its brute-force neighbour search excluded
+    # (the GPU step excludes the list build too); the search's own time and
+    # the rate with it are reported beside
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-
-        n_s = min(args.cpu_structures, host.num_structures)
-        sub = host.subset(range(n_s))
-        om = O.Model(**w.model)
-        cores = args.cpu_threads if args.cpu_threads > 0 else min(os.cpu_count() or 1, 16)
-        th_h = th.double().cpu().numpy()
-        qs_h = qs.double().cpu().numpy()
-        a0 = int(sub.atom_offset[-1])
-        Et_h = targets.energy[:n_s].cpu().numpy()
-        Ft_h = targets.force[:a0].double().cpu().numpy()
-        Wt_h = targets.virial[:n_s].cpu().numpy()
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            O.loss_and_grad(om, th_h, qs_h, sub, Et_h, Ft_h, Wt_h, w.lambdas, nthreads=cores)
-            reps += 1
-            dt = time.perf_counter() - t0
-            if dt >= args.cpu_seconds:
-                break
-        rate = reps * n_s / dt
-        cpu = {"value": round(rate, 2), "unit": "structures/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {n_s} structures of the workload x {reps} repetitions, FP64 loss + gradient "
-                         f"(the oracle's brute-force neighbour search included), {dt:.1f} s"}
-        log(f"cpu oracle {rate:.1f} structures/s on {cores} threads ({reps} x {n_s} structures, {dt:.1f} s)")
+        cpu = cpu_baseline(args, w, host, th, qs, targets, log)
 
     out = {
         "metric": "structures/s for NEP E/F/virial loss+param-grad; % HBM/VALU roofline",
@@ -475,6 +557,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_per_step_spread": {"median": round(p50, 4), "p10": round(p10, 4), "p90": round(p90, 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -69,6 +69,8 @@ def lib():
         L.orc_batch_loss_grad.argtypes = [mp, dp, dp, C.c_int, lp, dp, dp, ip, dp, dp, dp,
                                           C.POINTER(C.c_ubyte), C.c_double, C.c_double, C.c_double,
                                           dp, dp, dp, dp, dp, C.c_int]
+        L.orc_search_seconds.argtypes = [C.c_int]
+        L.orc_search_seconds.restype = C.c_double
         L.orc_wigner3j.argtypes = [C.c_int] * 6
         L.orc_wigner3j.restype = C.c_double
         L.orc_real_sh.argtypes = [C.c_int, dp, dp, dp]
@@ -219,6 +221,12 @@ def loss_and_grad(model: Model, theta, qscale, batch, E_t, F_t, W_t, lambdas=(1.
     if rc:
         raise RuntimeError(f"orc_batch_loss_grad failed ({rc})")
     return loss, grad, E, F, W
+
+
+def search_seconds(reset: bool = False) -> float:
+    """Seconds the brute-force neighbour search has taken so far, summed over
+    threads (timing only); ``reset`` zeroes the counter."""
+    return float(lib().orc_search_seconds(1 if reset else 0))
 
 
 def wigner3j(j1, j2, j3, m1, m2, m3):

@@ -40,6 +40,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -587,8 +588,26 @@ typedef struct {
     long* first; /* [n+1] */
 } struct_pairs;
 
+/* Seconds spent in the brute-force search, summed over threads (timing only:
+ * lets a benchmark report the evaluation without the search). */
+static double g_search_seconds = 0.0;
+
+double orc_search_seconds(int reset) {
+    double v;
+#pragma omp critical(orc_search_timer)
+    {
+        v = g_search_seconds;
+        if (reset) g_search_seconds = 0.0;
+    }
+    return v;
+}
+
 static int make_struct_pairs(const orc_model* m, int n, const double* cell, const double* pos, struct_pairs* sp) {
+    const double t0 = omp_get_wtime();
     sp->np = brute_neighbors(n, cell, pos, m->rc_r, &sp->list);
+    const double dt = omp_get_wtime() - t0;
+#pragma omp critical(orc_search_timer)
+    g_search_seconds += dt;
     if (sp->np < 0) return -1;
     sp->first = (long*)calloc((size_t)n + 1, sizeof(long));
     for (long p = 0; p < sp->np; p++) sp->first[sp->list[p].i + 1]++;
