@@ -179,15 +179,14 @@ class AutogradNEP:
 
     def loss(self, theta, q_scale, E_t, F_t, W_t, lambdas=(1.0, 1.0, 0.1), has_virial=None):
         E, F, W = self.energy_forces_virial(theta, q_scale, create_graph=True)
-        dE = (((E - E_t) / self.na_s) ** 2).mean()
+        # structures without atoms take no part (N_s and N_v count structures with atoms)
+        nz = self.na_s > 0
+        dE = (((E - E_t)[nz] / self.na_s[nz]) ** 2).mean()
         dF = ((F - F_t) ** 2).sum() / (3 * self.Na)
-        rw = ((W - W_t) / self.na_s[:, None]) ** 2
-        if has_virial is not None:
-            hv = has_virial.to(rw.dtype)
-            nv = hv.sum()
-            dV = (rw.sum(1) * hv).sum() / (9 * nv) if nv > 0 else rw.sum() * 0
-        else:
-            dV = rw.sum() / (9 * self.Ns)
+        rw = ((W - W_t)[nz] / self.na_s[nz][:, None]) ** 2
+        hv = (has_virial[nz] if has_virial is not None else torch.ones_like(self.na_s[nz])).to(rw.dtype)
+        nv = hv.sum()
+        dV = (rw.sum(1) * hv).sum() / (9 * nv) if nv > 0 else rw.sum() * 0
         L = lambdas[0] * dE + lambdas[1] * dF + lambdas[2] * dV
         return L, torch.stack([L, dE, dF, dV]).detach()
 

@@ -100,7 +100,9 @@ typedef struct {
 } nep_model;
 
 /* A packed batch of fully periodic structures. Structure s owns atoms
- * atom_offset[s] .. atom_offset[s+1]-1; every structure has at least one atom. */
+ * atom_offset[s] .. atom_offset[s+1]-1. A structure may be empty (nep_gather_batch
+ * makes one for an out-of-range id): its E_s and W_s are 0 and it takes no part
+ * in the loss (N_s and N_v of Eqs. 4-7 count only structures with atoms). */
 typedef struct {
     int32_t num_structures;     /* Ns >= 0 */
     int64_t num_atoms;          /* Na = atom_offset[Ns] */
@@ -225,7 +227,8 @@ nep_status nep_zbl_add(const nep_model* model, const nep_zbl* zbl, const nep_bat
                        void* stream);
 
 /* The weighted loss L = lambda_e Delta_E + lambda_f Delta_F + lambda_v Delta_V
- * (Eqs. 4-7; N_s, N_a, N_a^s over the batch; Delta_V over labelled structures)
+ * (Eqs. 4-7; N_s, N_a, N_a^s over the batch's non-empty structures; Delta_V over
+ * the labelled ones)
  * and its gradient dL/dtheta (the g_t of Adam, Eq. 8), computed analytically.
  *   loss [4] double device: {L, Delta_E, Delta_F, Delta_V};
  *   grad [P] dtype, overwritten;

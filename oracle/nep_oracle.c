@@ -903,17 +903,29 @@ int orc_batch_loss_grad(const orc_model* m, const double* theta, const double* q
         free(W);
         return -2;
     }
-    int Nv = 0;
-    for (int s = 0; s < Ns; s++) Nv += has_virial ? (has_virial[s] != 0) : 1;
+    /* Eqs. 4-7 average per-atom residuals over the batch's structures; a
+     * structure without atoms has no per-atom residual (N_a^s = 0) and is not
+     * counted in N_s, nor in the number N_v of labelled structures. */
+    int Nv = 0, Nsa = 0;
+    for (int s = 0; s < Ns; s++) {
+        if (off[s + 1] == off[s]) continue;
+        Nsa++;
+        Nv += has_virial ? (has_virial[s] != 0) : 1;
+    }
     double dE = 0.0, dF = 0.0, dV = 0.0;
     double* ebar = (double*)malloc(sizeof(double) * (Ns > 0 ? Ns : 1));
     double* ub = (double*)malloc(sizeof(double) * 3 * (Na > 0 ? Na : 1));
     double* Ub = (double*)malloc(sizeof(double) * 9 * (Ns > 0 ? Ns : 1));
     for (int s = 0; s < Ns; s++) {
         double na = (double)(off[s + 1] - off[s]);
+        if (na == 0.0) {
+            ebar[s] = 0.0;
+            for (int c = 0; c < 9; c++) Ub[9 * s + c] = 0.0;
+            continue;
+        }
         double r = (E[s] - Et[s]) / na;
-        dE += r * r / Ns;
-        ebar[s] = lam_e * 2.0 * (E[s] - Et[s]) / (Ns * na * na);
+        dE += r * r / Nsa;
+        ebar[s] = lam_e * 2.0 * (E[s] - Et[s]) / (Nsa * na * na);
         int hv = has_virial ? (has_virial[s] != 0) : 1;
         for (int c = 0; c < 9; c++) {
             double rw = (W[9 * s + c] - Wt[9 * s + c]) / na;

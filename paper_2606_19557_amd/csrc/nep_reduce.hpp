@@ -14,7 +14,8 @@ constexpr int kRedBlock = 256;
 //   ebar_s = dL/dE_s = 2 lam_e (E_s - E*_s) / (N_s N_a^s^2),
 //   ubar_i = dL/dF_i = 2 lam_f (F_i - F*_i) / (3 N_a),
 //   Ubar_s = dL/dW_s = 2 lam_v (W_s - W*_s) / (9 N_v N_a^s^2)  (labelled s only).
-// Structures without atoms contribute nothing.
+// Structures without atoms take no part: N_s and N_v count only structures
+// with atoms (N_a^s = 0 leaves Eq. 4's per-atom residual undefined).
 template <typename R>
 __global__ void __launch_bounds__(kRedBlock)
 k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restrict__ E_at,
@@ -23,8 +24,9 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
             double lam_e, double lam_f, double lam_v, double* __restrict__ E_out, double* __restrict__ W_out,
             double* __restrict__ ebar, double* __restrict__ Ubar, R* __restrict__ ubar,
             double* __restrict__ lossp) {
-    // E, W[9], the force residual and the number of labelled structures
-    constexpr int NV = 12, WAVES = kRedBlock / 64;
+    // E, W[9], the force residual, the number of labelled structures and the
+    // number of structures with atoms
+    constexpr int NV = 13, WAVES = kRedBlock / 64;
     __shared__ double part[WAVES][NV];
     const int s = blockIdx.x;
     const long a0 = off[s], a1 = off[s + 1];
@@ -58,7 +60,11 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
         }
     }
     if (loss)
-        for (int t = threadIdx.x; t < Ns; t += kRedBlock) acc[11] += has_v ? double(has_v[t] != 0) : 1.0;
+        for (int t = threadIdx.x; t < Ns; t += kRedBlock) {
+            const bool atoms = off[t + 1] > off[t];
+            acc[11] += (atoms && (has_v ? has_v[t] != 0 : true)) ? 1.0 : 0.0;
+            acc[12] += atoms ? 1.0 : 0.0;
+        }
     // wave sums by shuffles, one barrier, then the waves' sums in wave order
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
@@ -91,10 +97,10 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
         lossp[s * 3 + 2] = 0.0;
         return;
     }
-    const double Nv = res[11];
+    const double Nv = res[11], Nsa = res[12];
     const double dE = E - Ets;
-    ebar[s] = 2.0 * lam_e * dE / (double(Ns) * na * na);
-    lossp[s * 3 + 0] = (dE / na) * (dE / na) / double(Ns);
+    ebar[s] = 2.0 * lam_e * dE / (Nsa * na * na);
+    lossp[s * 3 + 0] = (dE / na) * (dE / na) / Nsa;
     lossp[s * 3 + 1] = res[10] / (3.0 * double(Na));
     double dv = 0.0;
     for (int c = 0; c < 9; ++c) {

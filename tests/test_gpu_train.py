@@ -100,3 +100,20 @@ def test_gather_out_of_range_ids_are_empty_structures():
     P = dnb.num_pairs
     assert torch.equal(gnb.pairs[:P], dnb.pairs[:P]) and torch.equal(gnb.reverse[:P], dnb.reverse[:P])
     assert torch.equal(gb.positions, direct.positions)
+    # the empty structures take no part in the loss: the gathered batch's loss and
+    # gradient equal the oracle's on the two structures alone (and on the
+    # gathered batch with its empty entries)
+    import oracle as O
+    from helpers import rel_err
+
+    m = O.Model(**md)
+    sub = b.subset([2, 0])
+    a0 = np.concatenate([np.arange(b.atom_offset[s], b.atom_offset[s + 1]) for s in (2, 0)])
+    Et, Ft, Wt = tg
+    lam = (1.0, 1.0, 0.1)
+    gtg.lambdas = lam
+    loss, g = N.nep_loss_and_grad(model, theta, qs, gb, gnb, gtg)
+    lo, go, *_ = O.loss_and_grad(m, theta.double().cpu().numpy(), qs.double().cpu().numpy(), sub, Et[[2, 0]],
+                                 Ft[a0], Wt[[2, 0]], lam)
+    assert rel_err(loss.cpu().numpy(), lo) < 1e-5
+    assert rel_err(g.double().cpu().numpy(), go) < 1e-4

@@ -472,6 +472,34 @@ def test_loss_value_definition():
     assert np.allclose(loss, [lam[0] * dE + lam[1] * dF + lam[2] * dV, dE, dF, dV], rtol=1e-13)
 
 
+def test_empty_structures_take_no_part():
+    """A structure without atoms has no per-atom residual in Eqs. (4)-(7) (N_a^s = 0):
+    inserting empty structures, labelled or not, leaves the loss and its gradient
+    unchanged, and the hand-computed loss of the non-empty ones holds."""
+    m = model_alloy()
+    rng = np.random.default_rng(3)
+    full = [S.fcc_structure(rng, 9, a=4.0, sigma=0.2, num_types=3), S.bcc_structure(rng, 8, a=3.2, sigma=0.2,
+                                                                                  num_types=3)]
+    empty = (np.eye(3) * 7.0, np.zeros((0, 3)), np.zeros(0, np.int32))
+    b0 = S.pack(full, 3)
+    b1 = S.pack([empty, full[0], empty, full[1], empty], 3)
+    theta, s = theta_and_scale(m, b0)
+    Et, Ft, Wt = _targets(b0, 5)
+    hv0 = np.array([1, 0], np.uint8)
+    lam = (1.0, 1.0, 0.1)
+    l0, g0, E0, F0, W0 = O.loss_and_grad(m, theta, s, b0, Et, Ft, Wt, lam, has_virial=hv0)
+    Et1 = np.array([3.0, Et[0], -2.0, Et[1], 1.0])
+    Wt1 = np.stack([np.full(9, 5.0), Wt[0], np.ones(9), Wt[1], np.zeros(9)])
+    hv1 = np.array([1, 1, 0, 0, 1], np.uint8)
+    l1, g1, E1, F1, W1 = O.loss_and_grad(m, theta, s, b1, Et1, Ft, Wt1, lam, has_virial=hv1)
+    assert np.allclose(l1, l0, rtol=1e-14, atol=0) and np.allclose(g1, g0, rtol=1e-12, atol=1e-15)
+    assert np.array_equal(E1[[0, 2, 4]], np.zeros(3)) and np.array_equal(W1[[0, 2, 4]], np.zeros((3, 9)))
+    na = b0.counts()
+    dE = np.mean(((E0 - Et) / na) ** 2)
+    dV = np.sum(((W0[0] - Wt[0]) / na[0]) ** 2) / 9.0
+    assert np.allclose(l0[[1, 3]], [dE, dV], rtol=1e-13)
+
+
 # ------------------------------------------------------------------- Adam
 
 
