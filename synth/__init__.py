@@ -14,4 +14,4 @@ from .structures import (  # noqa: F401
     random_packing,
     pack,
 )
-from .workloads import WORKLOADS, Workload, workload_batch, draw_theta  # noqa: F401
+from .workloads import WORKLOADS, Workload, workload_batch, draw_theta, random_targets  # noqa: F401

@@ -136,3 +136,16 @@ def draw_theta(num_params: int, seed: int, std: float = 0.1) -> np.ndarray:
     """Seeded N(0, std^2) draw of every parameter (float64)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.normal(0.0, std, size=int(num_params))
+
+
+def random_targets(batch, seed: int, e_std: float = 0.1, f_std: float = 0.5, w_std: float = 0.05):
+    """Seeded random reference data for a packed batch: energies E_s = N_s * N(0, e_std^2),
+    forces N(0, f_std^2) per component, symmetric virials N_s * N(0, w_std^2) per entry
+    (N_s = atoms of the structure). Values only; no potential is evaluated."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = np.diff(np.asarray(batch.atom_offset)).astype(np.float64)
+    E = n * rng.normal(0.0, e_std, size=len(n))
+    F = rng.normal(0.0, f_std, size=(int(batch.num_atoms), 3))
+    w = rng.normal(0.0, w_std, size=(len(n), 3, 3))
+    W = (n[:, None, None] * 0.5 * (w + w.transpose(0, 2, 1))).reshape(len(n), 9)
+    return E, F, W

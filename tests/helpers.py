@@ -79,3 +79,14 @@ def small_alloy_batch(seed=5, n_struct=5):
         else:
             structs.append(S.fcc_structure(rng, 10 + 3 * k, a=4.0, sigma=0.2, strain=0.02, num_types=3))
     return S.pack(structs, 3)
+
+
+def rel_err_plain(x, ref, floor_frac):
+    """max_i |x_i - ref_i| / |ref_i| over the entries with |ref_i| >= floor_frac * max|ref|:
+    the plain per-element relative error of the components that carry the array."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    big = np.abs(ref) >= floor_frac * np.abs(ref).max() if ref.size else np.zeros(0, bool)
+    if not big.any():
+        return 0.0
+    return float(np.max(np.abs(x[big] - ref[big]) / np.abs(ref[big])))
