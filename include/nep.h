@@ -281,6 +281,23 @@ nep_status nep_train_step(const nep_model* model, void* theta, const void* q_sca
                           int64_t t, const nep_adam_cfg* cfg, double* loss, void* grad, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* nep_train_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the workspace taken from a static device
+ * array of 128 MiB inside the library instead of a caller argument. Each GPU
+ * the library runs on holds its own copy of that array from the first call on
+ * it until the process ends; the call runs on the current device (stream must
+ * belong to it) and calls no hipMalloc, hipFree or other allocating routine.
+ * All calls on one GPU share the array and it keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap on one GPU (two
+ * streams, two host threads) race and give undefined results.
+ * Returns NEP_ERR_WORKSPACE, before touching the device, when the batch needs
+ * more than 128 MiB of workspace (nep_workspace_size); other arguments and
+ * errors as in nep_train_step. */
+nep_status nep_train_step_noalloc(const nep_model* model, void* theta, const void* q_scale, const nep_batch* batch,
+                                  const nep_neighbors* nbr, const nep_targets* targets, void* m, void* v, void* vmax,
+                                  int64_t t, const nep_adam_cfg* cfg, double* loss, void* grad, void* stream);
+
 /* Eq. (2) factors from descriptors: q_scale[nu] = 1/(max_i q[i][nu] - min_i q[i][nu]),
  * or 1 where that range is below 1e-10. descriptor [Na][D], q_scale [D], dtype. */
 nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int32_t dtype, const void* descriptor,

@@ -309,6 +309,36 @@ static nep_status check_adam(const nep_adam_cfg* cfg, int64_t t) {
     return NEP_OK;
 }
 
+// ------------------------------------------ allocation-free training step
+
+// Workspace of nep_train_step_noalloc: a fixed device array in this code
+// object, one copy on each GPU the library runs on, held until the process
+// ends. Host code never passes the array's name to a kernel: it takes the
+// device address from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with it current).
+static nep_status scratch_address(void** out) {
+    int dev = -1;
+    NEP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(NEP_ERR_UNSUPPORTED, "device %d outside the %d devices the scratch table covers", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        NEP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(NEP_ERR_HIP, "hipGetSymbolAddress returned a null scratch address on device %d", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NEP_OK;
+}
+
 }  // namespace nep
 
 using namespace nep;
@@ -538,6 +568,33 @@ nep_status nep_train_step(const nep_model* model, void* theta, const void* q_sca
     c.v = v;
     c.vmax = vmax;
     return dispatch(c, se);
+}
+
+nep_status nep_train_step_noalloc(const nep_model* model, void* theta, const void* q_scale, const nep_batch* batch,
+                                  const nep_neighbors* nbr, const nep_targets* tg, void* m, void* v, void* vmax,
+                                  int64_t t, const nep_adam_cfg* cfg, double* loss, void* grad, void* stream) {
+    clear_error();
+    // the size check runs on the host before anything touches the device
+    Dims d;
+    Plan plan;
+    nep_status s;
+    if ((s = make_dims(model, &d))) return s;
+    if ((s = check_batch(batch))) return s;
+    if ((s = check_nbr(nbr, batch))) return s;
+    if ((s = resolve_plan(model->plan, &plan))) return s;
+    const size_t need =
+        make_layout(d, plan, model->dtype == NEP_F64, batch->num_structures, long(batch->num_atoms), long(nbr->num_pairs))
+            .total;
+    if (need > kScratchBytes)
+        return fail(NEP_ERR_WORKSPACE,
+                    "batch of %d structures, %lld atoms, %lld pairs needs %zu bytes of workspace; the static "
+                    "scratch of nep_train_step_noalloc holds %zu (use nep_train_step with a workspace)",
+                    batch->num_structures, (long long)batch->num_atoms, (long long)nbr->num_pairs, need,
+                    kScratchBytes);
+    void* ws = nullptr;
+    if ((s = scratch_address(&ws))) return s;
+    return nep_train_step(model, theta, q_scale, batch, nbr, tg, m, v, vmax, t, cfg, loss, grad, ws, kScratchBytes,
+                          stream);
 }
 
 nep_status nep_descriptor_scale(int64_t num_atoms, int64_t num_descriptors, int32_t dtype, const void* descriptor,

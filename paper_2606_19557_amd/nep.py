@@ -22,7 +22,8 @@ NEP_F32, NEP_F64 = 0, 1
 
 EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_gather_batch", "nep_forward",
            "nep_loss_and_grad", "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale",
-           "nep_last_error", "nep_profile_enable", "nep_profile_read", "nep_zbl_add", "nep_train_step")
+           "nep_last_error", "nep_profile_enable", "nep_profile_read", "nep_zbl_add", "nep_train_step",
+           "nep_train_step_noalloc")
 
 
 class NepError(RuntimeError):
@@ -102,6 +103,8 @@ def lib():
         L.nep_train_step.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
                                      C.POINTER(c_targets), vp, vp, vp, i64, C.POINTER(c_adam), vp, vp, vp,
                                      C.c_size_t, vp]
+        L.nep_train_step_noalloc.argtypes = [C.POINTER(c_model), vp, vp, C.POINTER(c_batch), C.POINTER(c_neighbors),
+                                             C.POINTER(c_targets), vp, vp, vp, i64, C.POINTER(c_adam), vp, vp, vp]
         L.nep_descriptor_scale.argtypes = [i64, i64, i32, vp, vp, vp]
         L.nep_zbl_add.argtypes = [C.POINTER(c_model), C.POINTER(c_zbl), C.POINTER(c_batch), C.POINTER(c_neighbors),
                                   C.c_double, vp, vp, vp, vp, C.c_size_t, vp]
@@ -501,6 +504,18 @@ def nep_train_step(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, t
     _check(lib().nep_train_step(C.byref(mm), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), C.byref(tg),
                                 _ptr(m), _ptr(v), _ptr(vmax), int(t), C.byref(c), _ptr(loss), _ptr(grad), _ptr(ws),
                                 ws.numel(), _stream()))
+    return loss, grad
+
+
+def nep_train_step_noalloc(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, targets: Targets, m, v,
+                           vmax, t: int, cfg: AdamConfig, grad, loss):
+    """nep_train_step with the library's static device workspace (no allocation
+    anywhere in the call): the caller passes every output (grad [P], loss [4]
+    f64); returns (loss, grad)."""
+    mm, b, cn, tg, c = model.c(), batch.c(), nbr.c(), targets.c(), cfg.c()
+    _check(lib().nep_train_step_noalloc(C.byref(mm), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn),
+                                        C.byref(tg), _ptr(m), _ptr(v), _ptr(vmax), int(t), C.byref(c), _ptr(loss),
+                                        _ptr(grad), _stream()))
     return loss, grad
 
 
