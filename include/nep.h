@@ -71,7 +71,9 @@ typedef struct {
     int32_t team_descriptor;   /* lanes per atom in the descriptor sweep: 4, 8 or 16 (default 8) */
     int32_t team_force;        /* lanes per atom in the force sweep and force gather (default 8) */
     int32_t team_tangent;      /* lanes per atom in the tangent sweep (default 8) */
-    int32_t team_coeff_grad;   /* lanes per atom in the angular coefficient-gradient sweep: 4, 8, 16 or 32 (default 8) */
+    int32_t team_coeff_grad;   /* lanes per atom in the angular coefficient-gradient sweep: 4, 8, 16 or 32 (default 8);
+                                  a team size whose LDS block (T^2 accumulator blocks) exceeds a CU's 160 KB runs
+                                  with 32-lane teams */
     int32_t coeff_grad_blocks; /* grid cap of that sweep = its FP64 partial rows, 1..65536 (default 2048) */
     int32_t outer_chunk;       /* atoms per work item of the network/radial outer products, 8..4096 (default 64) */
     int32_t network;           /* per-species network passes: 1 = matrix-core tiles of 32 atoms (16 in FP64),
@@ -79,6 +81,9 @@ typedef struct {
                                   (scalar) operands; 3 = inside the descriptor and tangent sweeps, each
                                   atom's team splitting the hidden units (no network launches), the
                                   descriptor sweep then also running the force pass; default 1 */
+    int32_t coeff_grad_rows;   /* angular coefficient-gradient sweep: 0 = teams of team_coeff_grad lanes, one pair
+                                  per lane (default); 1, 2 or 3 = moment rows per lane: ceil(N_A / rows) lanes per
+                                  atom, each running every pair of its atom for its rows (team_coeff_grad unused) */
 } nep_plan;
 
 /* Model hyper-parameters (the model keys of the paper's input file, Table I). */
@@ -313,6 +318,10 @@ const char* nep_last_error(void);
  * returns the number of distinct kernels in *count. enable(0) stops and clears. */
 nep_status nep_profile_enable(int32_t on);
 nep_status nep_profile_read(int32_t cap, char (*names)[64], int64_t* launches, double* total_ms, int32_t* count);
+/* Restrict that recording to launches of one kernel (its name as nep_profile_read
+ * reports it; host string, copied), so a timed loop carries two events per
+ * launch of that kernel only; NULL or "" records every kernel again. */
+nep_status nep_profile_only(const char* kernel_name);
 
 #ifdef __cplusplus
 }

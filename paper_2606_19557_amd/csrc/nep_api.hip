@@ -39,16 +39,33 @@ struct ProfRec {
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static std::vector<ProfRec*> g_prof;
+// records of cleared profiles, their events kept for reuse (no event creation
+// while a timed loop runs once the pool has grown)
+static std::vector<ProfRec*> g_prof_pool;
+// when not empty, only launches of this kernel name are timed
+static std::string g_prof_only;
 
 bool profiling_on() { return g_prof_on; }
 
 void profile_begin(const char* name, hipStream_t st, void** token) {
-    ProfRec* r = new ProfRec{name, nullptr, nullptr};
-    if (hipEventCreate(&r->a) != hipSuccess || hipEventCreate(&r->b) != hipSuccess) {
-        delete r;
-        *token = nullptr;
-        return;
+    *token = nullptr;
+    ProfRec* r = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_only.empty() && g_prof_only != name) return;
+        if (!g_prof_pool.empty()) {
+            r = g_prof_pool.back();
+            g_prof_pool.pop_back();
+        }
     }
+    if (!r) {
+        r = new ProfRec{name, nullptr, nullptr};
+        if (hipEventCreate(&r->a) != hipSuccess || hipEventCreate(&r->b) != hipSuccess) {
+            delete r;
+            return;
+        }
+    }
+    r->name = name;
     (void)hipEventRecord(r->a, st);
     *token = r;
 }
@@ -62,11 +79,7 @@ void profile_end(void* token, hipStream_t st) {
 
 static void profile_clear() {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    for (ProfRec* r : g_prof) {
-        (void)hipEventDestroy(r->a);
-        (void)hipEventDestroy(r->b);
-        delete r;
-    }
+    for (ProfRec* r : g_prof) g_prof_pool.push_back(r);
     g_prof.clear();
 }
 
@@ -106,7 +119,7 @@ const ShapeEntry* find_shape(const Dims& d) {
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 nep_status resolve_plan(const nep_plan* p, Plan* out) {
-    Plan q{kTeam, kTeam, kTeam, kTeam, kMaxAngRows, kOuterChunk, kNetwork};
+    Plan q{kTeam, kTeam, kTeam, kTeam, kMaxAngRows, kOuterChunk, kNetwork, 0};
     if (p) {
         const int32_t teams[4] = {p->team_descriptor, p->team_force, p->team_tangent, p->team_coeff_grad};
         int* dst[4] = {&q.team_desc, &q.team_force, &q.team_tangent, &q.team_cg};
@@ -133,6 +146,9 @@ nep_status resolve_plan(const nep_plan* p, Plan* out) {
                 return fail(NEP_ERR_INVALID_ARG, "plan network %d is not 1, 2 or 3", p->network);
             q.network = p->network;
         }
+        if (p->coeff_grad_rows < 0 || p->coeff_grad_rows > 3)
+            return fail(NEP_ERR_INVALID_ARG, "plan coeff_grad_rows %d is not 0, 1, 2 or 3", p->coeff_grad_rows);
+        q.cg_rows = p->coeff_grad_rows;
     }
     *out = q;
     return NEP_OK;
@@ -172,8 +188,16 @@ Layout make_layout(const Dims& dm, const Plan& plan, bool f64, int Ns, long Na, 
     L.ebar = take(8 * ns);
     L.Ubar = take(8 * ns * 9);
     L.lossp = take(8 * ns * 3);
-    const long teams = kBlock / plan.team_cg;
-    const long tiles = (Na + teams - 1) / teams;
+    long tiles;
+    if (plan.cg_rows > 0) {
+        // row-owned sweep: one block of cg_rows_waves wavefronts per partial row
+        const CgRowsGeom g = cg_rows_geom(dm.T, dm.NA, dm.KA, dm.LM, int(r), plan.cg_rows);
+        const long per_block = long(g.teams) * cg_rows_waves(g.wave_bytes);
+        tiles = (Na + per_block - 1) / per_block;
+    } else {
+        const long teams = kBlock / plan.team_cg;
+        tiles = (Na + teams - 1) / teams;
+    }
     L.ang_rows = int(tiles < plan.cg_blocks ? tiles : plan.cg_blocks);
     if (L.ang_rows < 1) L.ang_rows = 1;
     // outer reduction: one species-tagged row per chunk of outer_chunk atoms of
@@ -659,7 +683,7 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
         auto it = a.find(k);
         return it == a.end() ? 0.0 : it->second;
     };
-    nep_plan best{8, 8, 8, 8, kMaxAngRows, kOuterChunk, kNetwork};
+    nep_plan best{8, 8, 8, 8, kMaxAngRows, kOuterChunk, kNetwork, 0};
     // phase 1: team sizes, all four sweeps at once; each kernel keeps its fastest
     {
         const int cand[3] = {4, 8, 16};
@@ -668,7 +692,7 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
                                    {"angular_coeff_grad", nullptr}};
         int32_t* field[4] = {&best.team_descriptor, &best.team_force, &best.team_tangent, &best.team_coeff_grad};
         for (int k = 0; k < 3; ++k) {
-            nep_plan p{cand[k], cand[k], cand[k], cand[k], kMaxAngRows, kOuterChunk, kNetwork};
+            nep_plan p{cand[k], cand[k], cand[k], cand[k], kMaxAngRows, kOuterChunk, kNetwork, 0};
             std::map<std::string, double> avg;
             nep_status s = measure(p, &avg);
             if (skippable(s)) {
@@ -697,10 +721,28 @@ nep_status nep_autotune(const nep_model* model, const void* theta, const void* q
         std::map<std::string, double> avg;
         nep_status s = measure(p, &avg);
         if (fits(s)) {
-            if (get(avg, "angular_coeff_grad") < tb[3]) best.team_coeff_grad = 32;
+            if (get(avg, "angular_coeff_grad") < tb[3]) {
+                best.team_coeff_grad = 32;
+                tb[3] = get(avg, "angular_coeff_grad");
+            }
         } else if (!skippable(s)) {
             g_prof_on = was_on;
             return s;
+        }
+        // and, in FP32, the row-owned form with 1, 2 or 3 moment rows per lane
+        for (int rows = 1; rows <= 3 && model->dtype == NEP_F32; ++rows) {
+            nep_plan pr = best;
+            pr.coeff_grad_rows = rows;
+            s = measure(pr, &avg);
+            if (skippable(s)) continue;
+            if (s) {
+                g_prof_on = was_on;
+                return s;
+            }
+            if (get(avg, "angular_coeff_grad") < tb[3]) {
+                tb[3] = get(avg, "angular_coeff_grad");
+                best.coeff_grad_rows = rows;
+            }
         }
     }
     // phase 2: grid of the coefficient sweep and chunk of the outer products
@@ -763,6 +805,13 @@ nep_status nep_profile_enable(int32_t on) {
     clear_error();
     if (!on) profile_clear();
     g_prof_on = on != 0;
+    return NEP_OK;
+}
+
+nep_status nep_profile_only(const char* kernel_name) {
+    clear_error();
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_only = kernel_name ? kernel_name : "";
     return NEP_OK;
 }
 

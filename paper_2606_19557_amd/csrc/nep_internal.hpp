@@ -49,7 +49,8 @@ enum class Mode { Descriptors, Forward, LossGrad, Backward };
 struct Plan {
     int team_desc, team_force, team_tangent, team_cg;
     int cg_blocks, outer_chunk;
-    int network;  // 1 = matrix-core tiles, 2 = lane per atom
+    int network;  // 1 = matrix-core tiles, 2 = lane per atom, 3 = inside the sweeps
+    int cg_rows;  // 0 = pair-per-lane coefficient sweep; 1..3 = moment rows per lane
 };
 
 // Team size (lanes per atom) of the pair sweeps and the grid defaults.
@@ -129,6 +130,16 @@ T with_team_size(int s, F&& f) {
         case 4: return f(std::integral_constant<int, 4>{});
         case 16: return f(std::integral_constant<int, 16>{});
         default: return f(std::integral_constant<int, 8>{});
+    }
+}
+// Calls f(std::integral_constant<int, R>) for rows r in {1, 2, 3} of the
+// row-owned coefficient sweep.
+template <typename T, class F>
+T with_cg_rows(int r, F&& f) {
+    switch (r) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        default: return f(std::integral_constant<int, 2>{});
     }
 }
 template <class F>

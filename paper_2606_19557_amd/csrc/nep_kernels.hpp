@@ -77,10 +77,15 @@ __device__ __forceinline__ void team_network_forward(int lane, const Dims& dm, c
         }
         const R t = tanh_<R>(acc), t2 = tanh_<R>(acc2);
         const R wm = w1[mu], wm2 = two ? w1[mu2] : R(0);
-        E += wm * t + wm2 * t2;
+        E += wm * t;
+        E += wm2 * t2;
         const R c = wm * (R(1) - t * t), c2 = wm2 * (R(1) - t2 * t2);
 #pragma unroll
-        for (int v = 0; v < D; ++v) ev[v] += w[v] * c + w2[v] * c2;
+        for (int v = 0; v < D; ++v) {
+            // two separate accumulations: each one fused multiply-add
+            ev[v] += w[v] * c;
+            ev[v] += w2[v] * c2;
+        }
         t_out[i * H + mu] = t;
         if (two) t_out[i * H + mu2] = t2;
     }
@@ -167,7 +172,10 @@ __device__ __forceinline__ void team_network_backward(int lane, const Dims& dm, 
         }
         const R c = R(-2) * wm * t * sp * da, c2 = R(-2) * wm2 * t2 * sp2 * da2;
 #pragma unroll
-        for (int v = 0; v < D; ++v) z[v] += wr(v) * c + wr2(v) * c2;
+        for (int v = 0; v < D; ++v) {
+            z[v] += wr(v) * c;
+            z[v] += wr2(v) * c2;
+        }
     };
     if (lane < H)
         step(lane, f.two ? lane + S : lane, f.two, f.t, f.t2, f.wm, f.wm2, [&](int v) { return f.w[v]; },
@@ -970,7 +978,8 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
 #pragma unroll
                             for (int e = 0; e < VEC; ++e) {
                                 const int lm = c * VEC + e;
-                                pn += bv[e] * Yd[lm].v + qv[e] * vdy[lm];
+                                pn += bv[e] * Yd[lm].v;
+                                pn += qv[e] * vdy[lm];
                                 rn += qv[e] * Yd[lm].v;
                             }
                         }
@@ -998,6 +1007,308 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
     }
     __syncthreads();
     for (int x = threadIdx.x; x < G_len; x += kBlock) partial[(long)blockIdx.x * G_len + x] = double(G[x]);
+}
+
+// ------------------------------------- angular coefficient grad, rows per lane
+
+// The moment adjoints of one row n of an atom (the terms of moment_adjoints
+// for entries n*LM .. n*LM + LM - 1): Q = dE_i/dA[n][.] and Bp = dPsi/dA[n][.].
+template <typename R, class Sh>
+__device__ __forceinline__ void row_adjoints(int n, const R* __restrict__ A, const R* __restrict__ dA,
+                                             const R* __restrict__ e, const R* __restrict__ ab, R (&Q)[Sh::LM],
+                                             R (&Bp)[Sh::LM]) {
+    constexpr int NR = Sh::NR, NA = Sh::NA, LM = Sh::LM, L = Sh::L;
+    const R* __restrict__ An = A + n * LM;
+    const R* __restrict__ dAn = dA + n * LM;
+    R el[L], al[L];
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+        el[l - 1] = e[NR + (l - 1) * NA + n];
+        al[l - 1] = ab[NR + (l - 1) * NA + n];
+    }
+    R a[LM], d[LM];
+#pragma unroll
+    for (int lm = 0; lm < LM; ++lm) {
+        a[lm] = An[lm];
+        d[lm] = dAn[lm];
+    }
+#pragma unroll
+    for (int lm = 0; lm < LM; ++lm) {
+        const int l = lm_degree<LM>(lm);
+        Q[lm] = R(2) * el[l - 1] * a[lm];
+        Bp[lm] = R(2) * al[l - 1] * a[lm] + R(2) * el[l - 1] * d[lm];
+    }
+    if (Sh::H4) {
+        const int i4 = NR + L * NA + n;
+        const R e4 = e[i4], a4 = ab[i4];
+        R g4[5], h4[5];
+        q4_grad<R>(a + 3, g4);
+        q4_hess_vec<R>(a + 3, d + 3, h4);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            Q[3 + m] += e4 * g4[m];
+            Bp[3 + m] += a4 * g4[m] + e4 * h4[m];
+        }
+    }
+    if (Sh::H5) {
+        const int i5 = NR + (L + (Sh::H4 ? 1 : 0)) * NA + n;
+        const R e5 = e[i5], a5 = ab[i5];
+        const R P = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+        const R dd = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            Q[m] += e5 * R(4) * P * a[m];
+            Bp[m] += a5 * R(4) * P * a[m] + e5 * (R(8) * dd * a[m] + R(4) * P * d[m]);
+        }
+    }
+}
+
+// Cursor over one atom's angular pairs in batches of up to S that stay inside
+// one neighbour-species segment: segment b, first pair kin of the batch inside
+// it, the segment's angular count and its first row offset. tab holds the
+// team's segment table: angular starts [T+1], then row offsets [T].
+struct SegCursor {
+    int b, kin, ang, pos;
+    __device__ __forceinline__ void next_segment(const int* tab, int T) {
+        kin = 0;
+        ang = 0;
+        do {
+            ++b;
+            if (b < T) ang = tab[b + 1] - tab[b];
+        } while (b < T && ang == 0);
+        pos = b < T ? tab[T + 1 + b] : 0;
+    }
+    __device__ __forceinline__ void first(const int* tab, int T) {
+        b = -1;
+        next_segment(tab, T);
+    }
+    template <int S>
+    __device__ __forceinline__ void advance(const int* tab, int T) {
+        if (b >= T) return;
+        kin += S;
+        if (kin >= ang) next_segment(tab, T);
+    }
+};
+
+// dL/dc_A[a][b][n][k] (the sum of k_angular_coeff_grad), rows per lane: a team
+// of S = ceil(N_A / ROWS) lanes per atom, lane l holding rows
+// n = l ROWS .. l ROWS + ROWS - 1 of the atom's Bp and Q in registers. Each
+// batch, the team's lanes evaluate one pair each (basis, harmonics and their
+// derivative along v) and publish (Y, v.dY, f, (v.r^) f') in their LDS slots;
+// every lane then runs the whole batch for its own rows, forming P_n and R_n
+// in full, so the outer product over k needs neither an exchange nor a team
+// sum. Batches stay inside one neighbour-species segment and each team walks
+// its atom's segments on its own; a lane adds its sums into the wavefront's
+// accumulator G[a][b] (LDS atomics, in the wavefront's fixed instruction
+// order: bitwise repeatable) when its team moves to another segment. Pair
+// records are loaded two batches ahead and the neighbours' seeds one batch
+// ahead. Each wavefront owns one G and walks its own tiles; the block's
+// wavefronts add their G in wavefront order into the block's partial row.
+template <typename R, class Sh, int ROWS>
+__global__ void __launch_bounds__(kBlock)
+k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
+                          const int64_t* __restrict__ row, const int* __restrict__ seg,
+                          const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar,
+                          const double* __restrict__ Ubar, const R* __restrict__ A_in, const R* __restrict__ dA_in,
+                          const R* __restrict__ e_in, const R* __restrict__ abar, double* __restrict__ partial) {
+    constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L, D = Sh::D;
+    constexpr CgRowsGeom GM = cg_rows_geom(1, NA, KA, LM, int(sizeof(R)), ROWS);
+    constexpr int S = GM.S, TEAMS = GM.teams, VEC = GM.vec, KAP = GM.kap, SLOT = GM.slot, TSTRIDE = GM.tstride;
+    static_assert(LM % VEC == 0 && KAP % VEC == 0 && SLOT % VEC == 0 && TSTRIDE % VEC == 0, "vector layout");
+    using V = typename VecOf<R>::type;
+    using X = MomentExchange<R, NA, LM, S>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = dm.T;
+    const CgRowsGeom gm = cg_rows_geom(T, NA, KA, LM, int(sizeof(R)), ROWS);
+    const int nw = blockDim.x / 64, wave = threadIdx.x / 64, wl = threadIdx.x % 64;
+    unsigned char* wbase = smem_raw + size_t(wave) * gm.wave_bytes;
+    R* G = reinterpret_cast<R*>(wbase);
+    const int G_len = T * T * NA * KA;
+    for (int x = wl; x < G_len; x += 64) G[x] = R(0);
+    const int team = wl / S, lane = wl % S;
+    const bool in_team = team < TEAMS;
+    R* myslots = reinterpret_cast<R*>(wbase + gm.off_slots) + (in_team ? team : 0) * TSTRIDE;
+    int* tab = reinterpret_cast<int*>(wbase + gm.off_tab) + (in_team ? team : 0) * (2 * T + 1);
+    const R rcA = R(dm.rcA), irA = R(1.0 / dm.rcA);
+    const int tiles = (Na + TEAMS - 1) / TEAMS;
+    for (int tile = blockIdx.x * nw + wave; tile < tiles; tile += gridDim.x * nw) {
+        const int i = tile * TEAMS + team;
+        const bool live = in_team && i < Na;
+        const int a = live ? types[i] : 0;
+        const int s = live ? atom_struct[i] : 0;
+        const int64_t p0 = live ? row[i] : 0;
+        R ui[3], U[9];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ui[d] = live ? ubar[(long)i * 3 + d] : R(0);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
+        if (live && lane == 0) {
+            int cum = 0, pos = 0;
+            for (int b = 0; b < T; ++b) {
+                const int tot = seg[(i * T + b) * 2], ang = seg[(i * T + b) * 2 + 1];
+                tab[b] = cum;
+                tab[T + 1 + b] = pos;
+                cum += ang;
+                pos += tot;
+            }
+            tab[T] = cum;
+        }
+        // this lane's rows of the atom's moment adjoints
+        R Q[ROWS][LM], Bp[ROWS][LM];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int n = lane * ROWS + r;
+            if (live && n < NA) {
+                row_adjoints<R, Sh>(n, A_in + (long)i * NA * LM, dA_in + (long)i * NA * LM, e_in + (long)i * D,
+                                    abar + (long)i * D, Q[r], Bp[r]);
+            } else {
+#pragma unroll
+                for (int lm = 0; lm < LM; ++lm) Q[r][lm] = Bp[r][lm] = R(0);
+            }
+        }
+        X::wave_fence();
+        // batches t, t+1, t+2 and the records of t and t+1
+        SegCursor cA{T, 0, 0, 0};
+        if (live) cA.first(tab, T);
+        SegCursor cB = cA;
+        cB.advance<S>(tab, T);
+        SegCursor cC = cB;
+        cC.advance<S>(tab, T);
+        auto fetch = [&](const SegCursor& c) {
+            Rec<R> rec{};
+            if (c.b < T && c.kin + lane < c.ang) rec = pairs[p0 + c.pos + c.kin + lane];
+            return rec;
+        };
+        Rec<R> recA = fetch(cA), recB = fetch(cB);
+        R ujA[3] = {R(0), R(0), R(0)};
+        if (cA.b < T && cA.kin + lane < cA.ang) {
+            const long j = rec_j(recA);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ujA[d] = ubar[j * 3 + d];
+        }
+        int cur_b = -1;
+        R acc[ROWS][KA];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+            for (int k = 0; k < KA; ++k) acc[r][k] = R(0);
+        auto flush = [&]() {
+            if (cur_b < 0) return;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int n = lane * ROWS + r;
+                if (n >= NA) continue;
+                R* g = G + ((a * T + cur_b) * NA + n) * KA;
+#pragma unroll
+                for (int k = 0; k < KA; ++k) {
+                    __hip_atomic_fetch_add(g + k, acc[r][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    acc[r][k] = R(0);
+                }
+            }
+        };
+        while (cA.b < T) {
+            // loads for the next batches: the records of t+2, then the
+            // neighbours' seeds of t+1 (issued last, so that waiting for them
+            // at the next batch does not also wait for the records)
+            const Rec<R> recC = fetch(cC);
+            R ujB[3] = {R(0), R(0), R(0)};
+            if (cB.b < T && cB.kin + lane < cB.ang) {
+                const long j = rec_j(recB);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ujB[d] = ubar[j * 3 + d];
+            }
+            // phase 1: this lane's pair of batch t into its slot
+            const int nq = cA.ang - cA.kin < S ? cA.ang - cA.kin : S;
+            if (lane < nq) {
+                const R rv[3] = {recA.x, recA.y, recA.z};
+                const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+                const R ir = R(1) / r;
+                const R u[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
+                R v[3];
+#pragma unroll
+                for (int be = 0; be < 3; ++be)
+                    v[be] = ui[be] - ujA[be] - (U[be] * rv[0] + U[3 + be] * rv[1] + U[6 + be] * rv[2]);
+                const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
+                // each value goes to the slot as soon as it is known, which keeps
+                // the basis and the harmonics from being live at once
+                R* sl = myslots + lane * SLOT;
+                {
+                    R fa[KA], fap[KA];
+                    cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
+#pragma unroll
+                    for (int k = 0; k < KAP; ++k) {
+                        sl[2 * LM + k] = k < KA ? fa[k] : R(0);
+                        sl[2 * LM + KAP + k] = k < KA ? fap[k] * vu : R(0);
+                    }
+                }
+                const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
+                D1<R> Yd[LM];
+                solid_harmonics<D1<R>, R, L>(dx, dy, dz, Yd);
+#pragma unroll
+                for (int lm = 0; lm < LM; ++lm) {
+                    sl[lm] = Yd[lm].v;
+                    sl[LM + lm] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
+                }
+            }
+            X::wave_fence();
+            // phase 2: the batch's pairs for this lane's rows
+            if (cA.b != cur_b) {
+                flush();
+                cur_b = cA.b;
+            }
+#pragma unroll 1
+            for (int q = 0; q < nq; ++q) {
+                const V* sl = reinterpret_cast<const V*>(myslots + q * SLOT);
+                R pn[ROWS], rn[ROWS];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) pn[r] = rn[r] = R(0);
+#pragma unroll
+                for (int c = 0; c < LM / VEC; ++c) {
+                    const V y = sl[c], dv = sl[LM / VEC + c];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r) {
+                            // one fused multiply-add per term
+                            pn[r] += Bp[r][c * VEC + e] * y[e];
+                            pn[r] += Q[r][c * VEC + e] * dv[e];
+                            rn[r] += Q[r][c * VEC + e] * y[e];
+                        }
+                }
+#pragma unroll
+                for (int c = 0; c < KAP / VEC; ++c) {
+                    const V f = sl[2 * LM / VEC + c], fp = sl[2 * LM / VEC + KAP / VEC + c];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int k = c * VEC + e;
+                        if (k >= KA) continue;
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r) {
+                            acc[r][k] += pn[r] * f[e];
+                            acc[r][k] += rn[r] * fp[e];
+                        }
+                    }
+                }
+            }
+            X::wave_fence();
+            cA = cB;
+            cB = cC;
+            cC.advance<S>(tab, T);
+            recA = recB;
+            recB = recC;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ujA[d] = ujB[d];
+        }
+        flush();
+        X::wave_fence();
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < G_len; x += blockDim.x) {
+        double sum = 0.0;
+        for (int w = 0; w < nw; ++w)
+            sum += double(reinterpret_cast<const R*>(smem_raw + size_t(w) * gm.wave_bytes)[x]);
+        partial[(long)blockIdx.x * G_len + x] = sum;
+    }
 }
 
 // ------------------------------------------ network and radial coefficient grad

@@ -28,14 +28,27 @@ nep_status run_shape(const Ctx& c) {
     auto team_grid = [&](int S) { return (Na + kBlock / S - 1) / (kBlock / S); };
     nep_status rs = NEP_OK;
 
-    // LDS of the angular-coefficient gradient block (dynamic; <= one CU's 160 KB)
-    const size_t cg_shm = with_cg_team_size<size_t>(c.plan.team_cg, [&](auto S_) {
-        return CoeffGradSmem<R, Sh, decltype(S_)::value>::bytes(dm.T);
-    });
+    // LDS of the angular-coefficient gradient block (dynamic; <= one CU's 160 KB).
+    // A block that does not fit with the plan's team size (many species in
+    // FP64: T^2 accumulator blocks) runs with 32-lane teams, the smallest block;
+    // the grid and the partial rows are the plan's either way.
+    int team_cg = c.plan.team_cg;
+    auto cg_bytes = [&](int S) {
+        return with_cg_team_size<size_t>(S, [&](auto S_) { return CoeffGradSmem<R, Sh, decltype(S_)::value>::bytes(dm.T); });
+    };
+    if (cg_bytes(team_cg) > 160 * 1024) team_cg = 32;
+    const size_t cg_shm = cg_bytes(team_cg);
+    // the row-owned form: LDS of one wavefront, wavefronts per block
+    const CgRowsGeom cg_rows_gm =
+        cg_rows_geom(dm.T, Sh::NA, Sh::KA, Sh::LM, int(sizeof(R)), c.plan.cg_rows > 0 ? c.plan.cg_rows : 1);
+    const int cg_rows_nw = cg_rows_waves(cg_rows_gm.wave_bytes);
     if (c.mode == Mode::LossGrad || c.mode == Mode::Backward) {
-        if (cg_shm > 160 * 1024)
+        if (c.plan.cg_rows > 0 && cg_rows_gm.wave_bytes > 160 * 1024)
+            return fail(NEP_ERR_UNSUPPORTED, "row-owned angular coefficient sweep needs %zu bytes of LDS per wavefront",
+                        cg_rows_gm.wave_bytes);
+        if (c.plan.cg_rows == 0 && cg_shm > 160 * 1024)
             return fail(NEP_ERR_UNSUPPORTED, "angular coefficient block of %d-lane teams needs %zu bytes of LDS",
-                        c.plan.team_cg, cg_shm);
+                        team_cg, cg_shm);
         if (OuterTiles<R>::lds_bytes(dm) > 160 * 1024 || dm.H > kBlock ||
             OuterTiles<R>::tiles(dm) > OuterTiles<R>::WAVES * OuterTiles<R>::MAXTW)
             return fail(NEP_ERR_UNSUPPORTED, "network of %d hidden units too large for the outer-product tiles", dm.H);
@@ -130,7 +143,22 @@ nep_status run_shape(const Ctx& c) {
             NEP_LAUNCH("network_backward", (k_network_backward<R, Sh>), dim3(net_grid), dim3(64), 0, st, dm, theta,
                        qscale, c.species_order, c.species_offset, c.atom_struct, Wd(L.ebar), Wr(L.dq), Wr(L.e),
                        Wr(L.t), Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
-        if ((rs = with_cg_team_size<nep_status>(c.plan.team_cg, [&](auto S_) -> nep_status {
+        if (c.plan.cg_rows > 0) {
+            if constexpr (sizeof(R) != 4)
+                return fail(NEP_ERR_UNSUPPORTED, "the row-owned coefficient sweep is built for FP32 only");
+            else if ((rs = with_cg_rows<nep_status>(c.plan.cg_rows, [&](auto R_) -> nep_status {
+                    constexpr int ROWS = decltype(R_)::value;
+                    const size_t shm = size_t(cg_rows_nw) * cg_rows_gm.wave_bytes;
+                    if (shm > 64 * 1024)
+                        NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad_rows<R, Sh, ROWS>),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
+                    NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad_rows<R, Sh, ROWS>), dim3(L.ang_rows),
+                               dim3(64 * cg_rows_nw), shm, st, dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs,
+                               Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dA), Wr(L.e), Wr(L.abar), Wd(L.ang_part));
+                    return NEP_OK;
+                })))
+                return rs;
+        } else if ((rs = with_cg_team_size<nep_status>(team_cg, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
                 if (cg_shm > 64 * 1024)
                     NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad<R, Sh, S>),

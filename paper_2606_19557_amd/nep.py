@@ -23,7 +23,7 @@ NEP_F32, NEP_F64 = 0, 1
 EXPORTS = ("nep_param_count", "nep_workspace_size", "nep_build_neighbors", "nep_gather_batch", "nep_forward",
            "nep_loss_and_grad", "nep_backward", "nep_autotune", "nep_adam_step", "nep_descriptor_scale",
            "nep_last_error", "nep_profile_enable", "nep_profile_read", "nep_zbl_add", "nep_train_step",
-           "nep_train_step_noalloc")
+           "nep_train_step_noalloc", "nep_profile_only")
 
 
 class NepError(RuntimeError):
@@ -35,7 +35,7 @@ class NepError(RuntimeError):
 class c_plan(C.Structure):
     _fields_ = [("team_descriptor", C.c_int32), ("team_force", C.c_int32), ("team_tangent", C.c_int32),
                 ("team_coeff_grad", C.c_int32), ("coeff_grad_blocks", C.c_int32), ("outer_chunk", C.c_int32),
-                ("network", C.c_int32)]
+                ("network", C.c_int32), ("coeff_grad_rows", C.c_int32)]
 
 
 class c_model(C.Structure):
@@ -111,6 +111,7 @@ def lib():
         L.nep_last_error.restype = C.c_char_p
         L.nep_profile_enable.argtypes = [i32]
         L.nep_profile_read.argtypes = [i32, vp, vp, vp, C.POINTER(i32)]
+        L.nep_profile_only.argtypes = [C.c_char_p]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_char_p if name == "nep_last_error" else i32
         _lib = L
@@ -143,10 +144,11 @@ class Plan:
     coeff_grad_blocks: int = 0
     outer_chunk: int = 0
     network: int = 0  # 1 = matrix-core tiles, 2 = one lane per atom, 3 = inside the sweeps
+    coeff_grad_rows: int = 0  # 0 = pair-per-lane coefficient sweep; 1-3 = moment rows per lane
 
     def c(self) -> c_plan:
         return c_plan(self.team_descriptor, self.team_force, self.team_tangent, self.team_coeff_grad,
-                      self.coeff_grad_blocks, self.outer_chunk, self.network)
+                      self.coeff_grad_blocks, self.outer_chunk, self.network, self.coeff_grad_rows)
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k in self.__dataclass_fields__}
@@ -467,7 +469,7 @@ def nep_autotune(model: Model, theta, q_scale, batch: Batch, nbr: Neighbors, tar
     _check(lib().nep_autotune(C.byref(m), _ptr(theta), _ptr(q_scale), C.byref(b), C.byref(cn), C.byref(tg),
                               _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), int(repeats), C.byref(out), _stream()))
     return Plan(out.team_descriptor, out.team_force, out.team_tangent, out.team_coeff_grad, out.coeff_grad_blocks,
-                out.outer_chunk, out.network)
+                out.outer_chunk, out.network, out.coeff_grad_rows)
 
 
 @dataclass
@@ -521,6 +523,11 @@ def nep_train_step_noalloc(model: Model, theta, q_scale, batch: Batch, nbr: Neig
 
 def nep_profile_enable(on: bool):
     _check(lib().nep_profile_enable(1 if on else 0))
+
+
+def nep_profile_only(kernel: str | None):
+    """Time only launches of `kernel` (None: every kernel) while profiling is on."""
+    _check(lib().nep_profile_only(None if kernel is None else kernel.encode()))
 
 
 def nep_profile_read(cap: int = 64):

@@ -109,13 +109,16 @@ def test_plan_validation_and_workspace():
     assert small < base < big
     # 32-lane teams exist only in the coefficient-gradient sweep
     assert nep.nep_workspace_size(m.with_plan(nep.Plan(team_coeff_grad=32)), 10, 5000, 200000) > 0
+    # the row-owned coefficient sweep (1-3 rows per lane) sizes its partial rows by its own tiles
+    for r in (1, 2, 3):
+        assert nep.nep_workspace_size(m.with_plan(nep.Plan(coeff_grad_rows=r)), 10, 5000, 200000) > 0
     # the three network variants share one workspace layout
     for k in (1, 2, 3):
         assert nep.nep_workspace_size(m.with_plan(nep.Plan(network=k)), 10, 5000, 200000) == base
     for bad in (nep.Plan(team_descriptor=5), nep.Plan(team_force=32), nep.Plan(team_tangent=32),
                 nep.Plan(team_descriptor=32), nep.Plan(team_coeff_grad=64), nep.Plan(coeff_grad_blocks=-1),
                 nep.Plan(outer_chunk=4), nep.Plan(outer_chunk=5000), nep.Plan(network=4),
-                nep.Plan(network=-1)):
+                nep.Plan(network=-1), nep.Plan(coeff_grad_rows=4), nep.Plan(coeff_grad_rows=-1)):
         with pytest.raises(nep.NepError) as e:
             nep.nep_workspace_size(m.with_plan(bad), 10, 5000, 200000)
         assert e.value.code == nep.NEP_ERR_INVALID_ARG
