@@ -190,7 +190,8 @@ nep_status run_shape(const Ctx& c) {
     }
     if (Na > 0 && dm.offB1 > 0)
         NEP_LAUNCH("reduce_stage", k_reduce_stage<kRedBlock / 64>, dim3(int((dm.offB1 + 63) / 64), kStageGroups), dim3(kRedBlock), 0,
-                   st, dm, Sh::NR * Sh::KR, Wd(L.outer_part), L.outer_rows, Wd(L.ang_part), L.ang_rows, Wd(L.stage));
+                   st, dm, Sh::NR * Sh::KR, Wd(L.outer_part), L.outer_rows, Wd(L.ang_part), L.ang_rows, Wd(L.stage),
+                   c.species_offset, L.outer_chunk);
     NEP_LAUNCH("final_reduce", (k_final_reduce<R>), dim3(int((dm.offB1 + kRedBlock) / kRedBlock)), dim3(kRedBlock), 0,
                st, dm, c.Ns, c.atom_offset, Wd(L.stage), Na > 0 ? kStageGroups : 0, Wd(L.ebar), Wd(L.lossp), c.lam_e,
                c.lam_f, c.lam_v, static_cast<R*>(c.grad), loss ? c.loss : nullptr, c.adam, c.adam_args,

@@ -129,15 +129,17 @@ k_seeds(int Ns, long Na, const double* __restrict__ dE, const R* __restrict__ dF
 // Gradient reduction, stage 1: block (x, g) sums, for 64 consecutive
 // parameters (one per lane, coalesced), the partial rows r = 4 g + w,
 // 4 g + w + 4 G, ... (w = wave) and adds the four wave sums in wave order into
-// stage[g][p]. Network and radial-coefficient columns come from the
-// species-tagged rows of the outer reduction, angular coefficients from the
-// angular rows.
+// stage[g][p]. Network and radial-coefficient columns of species a come from
+// species a's rows of the outer reduction only (its chunks of the
+// species-sorted atom list, in species order; soff and chunk give the range),
+// angular coefficients from the angular rows.
 constexpr int kStageGroups = 16;
 
 template <int WAVES_PER_BLOCK>
 __global__ void __launch_bounds__(kRedBlock)
 k_reduce_stage(Dims dm, int NRKR, const double* __restrict__ outer_part, int outer_rows,
-               const double* __restrict__ ang_part, int ang_rows, double* __restrict__ stage) {
+               const double* __restrict__ ang_part, int ang_rows, double* __restrict__ stage,
+               const int64_t* __restrict__ soff, int chunk) {
     __shared__ double red[kRedBlock];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = WAVES_PER_BLOCK;
     const int g = blockIdx.y, G = gridDim.y;
@@ -160,13 +162,14 @@ k_reduce_stage(Dims dm, int NRKR, const double* __restrict__ outer_part, int out
         // unconditional loads in unrolled loops: the rows' loads are in
         // flight together instead of one round trip per row
         if (col >= 0) {
-            const double tag = double(a);
+            // only species a's rows: the outer-product rows are the chunks of
+            // the species-sorted atom list in species order
+            int r0 = 0;
+            for (int t = 0; t < a; ++t) r0 += int((soff[t + 1] - soff[t] + chunk - 1) / chunk);
+            int r1 = r0 + int((soff[a + 1] - soff[a] + chunk - 1) / chunk);
+            r1 = r1 < outer_rows ? r1 : outer_rows;
 #pragma unroll 4
-            for (int r = g * waves + wave; r < outer_rows; r += step) {
-                const double* row = outer_part + (long)r * (W1 + 1);
-                const double t = row[0], v = row[1 + col];
-                s += t == tag ? v : 0.0;
-            }
+            for (int r = r0 + g * waves + wave; r < r1; r += step) s += outer_part[(long)r * (W1 + 1) + 1 + col];
         } else {
             const long angw = dm.offN - dm.offA;
 #pragma unroll 8
