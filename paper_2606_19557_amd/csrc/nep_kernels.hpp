@@ -38,6 +38,25 @@ struct SweepWaves {
     static constexpr int coeff_grad = (f32 && S >= 16) ? 3 : 1;
 };
 
+// Work item b of the species-sorted atom list: chunk k of species t, i.e.
+// sorted positions [soff[t] + k*chunk, min(soff[t+1], soff[t] + (k+1)*chunk)).
+// Items beyond the last chunk get t = -1.
+__device__ __forceinline__ void species_chunk(const int64_t* __restrict__ soff, int T, int chunk, int b, int* t_out,
+                                              long* lo, long* hi) {
+    *t_out = -1;
+    for (int t = 0; t < T; ++t) {
+        const long n = soff[t + 1] - soff[t];
+        const int c = int((n + chunk - 1) / chunk);
+        if (b < c) {
+            *t_out = t;
+            *lo = soff[t] + long(b) * chunk;
+            *hi = min(soff[t + 1], *lo + chunk);
+            return;
+        }
+        b -= c;
+    }
+}
+
 // ------------------------------------------------ network inside the sweeps
 
 // The per-species network of one atom split over its team (the fused plan):
@@ -229,7 +248,8 @@ struct DescTeamLds {
 // FUSE == 2: and runs the atom's force pass (h, own-direction F, virial).
 template <typename R, class Sh, int S, int FUSE>
 __global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::descriptor))
-k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
+k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__ order,
+             const int64_t* __restrict__ soff, int Na,
              const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
              R* __restrict__ q_out, R* __restrict__ A_out, R* __restrict__ S0_out, const R* __restrict__ qscale,
              R* __restrict__ E_out, R* __restrict__ e_out, R* __restrict__ t_out, const int* __restrict__ reverse,
@@ -240,11 +260,17 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
     __shared__ R xbuf[TEAMS * XR];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     R* tbuf = xbuf + team * XR;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
-    const bool live = i < Na;
     const int T = dm.T;
+    // a block takes TEAMS atoms of one species from the species-sorted list:
+    // the species, and with it every coefficient address, is uniform over the
+    // block (scalar loads)
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, TEAMS, xcd_tile(blockIdx.x, gridDim.x), &a, &lo, &hi);
+    if (a < 0) return;
+    const bool live = lo + team < hi;
+    const int i = live ? order[lo + team] : 0;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
-    const int a = live ? types[i] : 0;
     int64_t p = live ? row[i] : 0;
     R qR[NR];
 #pragma unroll
@@ -650,8 +676,8 @@ k_force_gather(int Na, const int64_t* __restrict__ row, const Rec<R>* __restrict
 // With NET the team then runs the atom's network Hessian-vector product.
 template <typename R, class Sh, int S, bool NET>
 __global__ void __launch_bounds__(kBlock, (SweepWaves<R, Sh, S>::tangent))
-k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types,
-          const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row, const int* __restrict__ seg,
+k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ order,
+          const int64_t* __restrict__ soff, const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row, const int* __restrict__ seg,
           const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar, const double* __restrict__ Ubar,
           const R* __restrict__ A_in, R* __restrict__ dq_out, R* __restrict__ dA_out, R* __restrict__ S1_out,
           const R* __restrict__ qscale, const double* __restrict__ ebar_s, const R* __restrict__ e_in,
@@ -664,11 +690,15 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ ty
     __shared__ R xbuf[TEAMS * X::TEAM_FLOATS];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
     R* tbuf = xbuf + team * X::TEAM_FLOATS;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
-    const bool live = i < Na;
     const int T = dm.T;
+    // one species per block, as in the descriptor sweep
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, TEAMS, xcd_tile(blockIdx.x, gridDim.x), &a, &lo, &hi);
+    if (a < 0) return;
+    const bool live = lo + team < hi;
+    const int i = live ? order[lo + team] : 0;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
-    const int a = live ? types[i] : 0;
     const int s = live ? atom_struct[i] : 0;
     int64_t p = live ? row[i] : 0;
     R ui[3], U[9];
@@ -1312,25 +1342,6 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ types, const in
 }
 
 // ------------------------------------------ network and radial coefficient grad
-
-// Work item b of the species-sorted atom list: chunk k of species t, i.e.
-// sorted positions [soff[t] + k*chunk, min(soff[t+1], soff[t] + (k+1)*chunk)).
-// Items beyond the last chunk get t = -1.
-__device__ __forceinline__ void species_chunk(const int64_t* __restrict__ soff, int T, int chunk, int b, int* t_out,
-                                              long* lo, long* hi) {
-    *t_out = -1;
-    for (int t = 0; t < T; ++t) {
-        const long n = soff[t + 1] - soff[t];
-        const int c = int((n + chunk - 1) / chunk);
-        if (b < c) {
-            *t_out = t;
-            *lo = soff[t] + long(b) * chunk;
-            *hi = min(soff[t + 1], *lo + chunk);
-            return;
-        }
-        b -= c;
-    }
-}
 
 // Matrix-core tile C[M][M] += A[M][KPI] B[KPI][M] of one wavefront.
 // FP32: v_mfma_f32_32x32x2f32 (M = 32, K = 2 per instruction);

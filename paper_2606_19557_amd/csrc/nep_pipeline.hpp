@@ -64,16 +64,16 @@ nep_status run_shape(const Ctx& c) {
     if (Na > 0 && (rs = with_team(c.plan.team_desc, [&](auto S_) -> nep_status {
             constexpr int S = decltype(S_)::value;
             if (fused_force)
-                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 2>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
-                           theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 2>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st,
+                           dm, theta, c.species_order, c.species_offset, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
                            Wr(L.t), c.reverse, hslots, Wr(L.Fown), Wr(L.Wat));
             else if (fused)
-                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 1>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
-                           theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 1>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st,
+                           dm, theta, c.species_order, c.species_offset, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), qscale, Wr(L.Eat), Wr(L.e),
                            Wr(L.t), nullptr, nullptr, nullptr, nullptr);
             else
-                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 0>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
-                           theta, c.types, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), nullptr, nullptr, nullptr,
+                NEP_LAUNCH("descriptor", (k_descriptor<R, Sh, S, 0>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st,
+                           dm, theta, c.species_order, c.species_offset, Na, c.row, c.seg, pairs, q, Wr(L.A), Wr(L.S0), nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, nullptr, nullptr);
             return NEP_OK;
         })))
@@ -122,13 +122,13 @@ nep_status run_shape(const Ctx& c) {
         if ((rs = with_team(c.plan.team_tangent, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
                 if (fused)
-                    NEP_LAUNCH("tangent", (k_tangent<R, Sh, S, true>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
-                               theta, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
+                    NEP_LAUNCH("tangent", (k_tangent<R, Sh, S, true>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st,
+                               dm, theta, c.species_order, c.species_offset, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
                                Wr(L.A), Wr(L.dq), Wr(L.dA), Wr(L.S1), qscale, Wd(L.ebar), Wr(L.e), Wr(L.t),
                                Wr(L.abar), Wr(L.alpha), Wr(L.beta), Wr(L.gam));
                 else
-                    NEP_LAUNCH("tangent", (k_tangent<R, Sh, S, false>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm,
-                               theta, c.types, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
+                    NEP_LAUNCH("tangent", (k_tangent<R, Sh, S, false>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st,
+                               dm, theta, c.species_order, c.species_offset, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
                                Wr(L.A), Wr(L.dq), Wr(L.dA), Wr(L.S1), nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr);
                 return NEP_OK;
