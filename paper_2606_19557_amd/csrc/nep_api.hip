@@ -9,6 +9,8 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
+#include <algorithm>
 #include <vector>
 
 #include "nep_internal.hpp"
@@ -81,6 +83,28 @@ static void profile_clear() {
     std::lock_guard<std::mutex> g(g_prof_mu);
     for (ProfRec* r : g_prof) g_prof_pool.push_back(r);
     g_prof.clear();
+}
+
+// --------------------------------------------------------------- occupancy
+
+int resident_blocks(const void* fn, int threads, size_t shm) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, int, int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    const auto key = std::make_tuple(fn, dev, threads, shm);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shm) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    const int n = std::max(1, per_cu) * std::max(1, cus);
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = n;
+    return n;
 }
 
 // ------------------------------------------------------------------ shapes
@@ -188,18 +212,21 @@ Layout make_layout(const Dims& dm, const Plan& plan, bool f64, int Ns, long Na, 
     L.ebar = take(8 * ns);
     L.Ubar = take(8 * ns * 9);
     L.lossp = take(8 * ns * 3);
-    long tiles;
     if (plan.cg_rows > 0) {
-        // row-owned sweep: one block of cg_rows_waves wavefronts per partial row
+        // row-owned sweep: one partial row per wavefront, at most cg_blocks
+        // wavefronts and no more than its species tiles, in whole blocks
         const CgRowsGeom g = cg_rows_geom(dm.T, dm.NA, dm.KA, dm.LM, int(r), plan.cg_rows);
-        const long per_block = long(g.teams) * cg_rows_waves(g.wave_bytes);
-        tiles = (Na + per_block - 1) / per_block;
+        const long nw = cg_rows_waves(g.wave_bytes);
+        const long tiles = (Na + g.teams - 1) / g.teams + dm.T;
+        long waves = tiles < plan.cg_blocks ? tiles : plan.cg_blocks;
+        if (waves < 1) waves = 1;
+        L.ang_rows = int((waves + nw - 1) / nw * nw);
     } else {
         const long teams = kBlock / plan.team_cg;
-        tiles = (Na + teams - 1) / teams;
+        const long tiles = (Na + teams - 1) / teams;
+        L.ang_rows = int(tiles < plan.cg_blocks ? tiles : plan.cg_blocks);
+        if (L.ang_rows < 1) L.ang_rows = 1;
     }
-    L.ang_rows = int(tiles < plan.cg_blocks ? tiles : plan.cg_blocks);
-    if (L.ang_rows < 1) L.ang_rows = 1;
     // outer reduction: one species-tagged row per chunk of outer_chunk atoms of
     // one species; at most ceil(Na / chunk) + T chunks.
     L.outer_chunk = plan.outer_chunk;

@@ -430,9 +430,9 @@ struct MomentExchange {
 // (Y[LM], v.dY[LM], f[KAP], (v.r^) f'[KAP], the basis rows padded to whole
 // 16-byte vectors), team blocks of TSTRIDE reals (a team stride of 4 words
 // modulo 32, so the broadcast reads of different teams spread over the banks),
-// and the bytes of one wavefront's LDS: its accumulator G[T][T][N_A][K_A],
-// the slots, and per team the segment table (angular starts [T+1], row
-// offsets [T]). Host and device use the same function.
+// and the bytes of one wavefront's LDS: its accumulator G[T][N_A][K_A] for one
+// atom species, the slots, and per team the segment table (angular starts
+// [T+1], row offsets [T]). Host and device use the same function.
 struct CgRowsGeom {
     int S, teams, vec, kap, slot, tstride;
     size_t off_slots, off_tab, wave_bytes;
@@ -447,16 +447,18 @@ __host__ __device__ constexpr CgRowsGeom cg_rows_geom(int T, int NA, int KA, int
     const int tw = g.S * g.slot * rbytes / 4;
     const int tsw = tw + ((4 - tw) % 32 + 32) % 32;
     g.tstride = tsw * 4 / rbytes;
-    const size_t G = size_t(T) * T * NA * KA * rbytes;
+    const size_t G = size_t(T) * NA * KA * rbytes;
     g.off_slots = (G + 15) / 16 * 16;
     g.off_tab = g.off_slots + size_t(g.teams) * g.tstride * rbytes;
     g.wave_bytes = (g.off_tab + size_t(g.teams) * (2 * T + 1) * 4 + 15) / 16 * 16;
     return g;
 }
-// Wavefronts per block of that sweep: four, two or one, the most whose LDS
-// fits one CU.
+// Wavefronts per block of that sweep: four, two or one, the most that still
+// lets a CU's 160 KB of LDS hold as many wavefronts as single-wavefront blocks
+// would (blocks are placed whole).
 __host__ __device__ constexpr int cg_rows_waves(size_t wave_bytes) {
-    return 4 * wave_bytes <= 160 * 1024 ? 4 : 2 * wave_bytes <= 160 * 1024 ? 2 : 1;
+    const size_t cu = 160 * 1024, per_cu = cu / wave_bytes;
+    return (cu / (4 * wave_bytes)) * 4 == per_cu ? 4 : (cu / (2 * wave_bytes)) * 2 == per_cu ? 2 : 1;
 }
 
 }  // namespace nep

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdint>
@@ -154,6 +155,11 @@ T with_cg_team_size(int s, F&& f) {
     if (s == 32) return f(std::integral_constant<int, 32>{});
     return with_team_size<T>(s, static_cast<F&&>(f));
 }
+
+// Blocks of `threads` threads with `shm` bytes of dynamic LDS that the current
+// device holds at once for kernel `fn` (occupancy per CU times CUs, cached per
+// kernel, device and launch shape); -1 if the runtime query fails.
+int resident_blocks(const void* fn, int threads, size_t shm);
 
 // Per-shape pipeline (forward / loss+grad / backward / descriptors).
 using ShapeFn = nep_status (*)(const Ctx&);

@@ -1136,11 +1136,12 @@ struct SegCursor {
 // wavefronts add their G in wavefront order into the block's partial row.
 template <typename R, class Sh, int ROWS>
 __global__ void __launch_bounds__(kBlock)
-k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ types, const int* __restrict__ atom_struct, int Na,
-                          const int64_t* __restrict__ row, const int* __restrict__ seg,
-                          const Rec<R>* __restrict__ pairs, const R* __restrict__ ubar,
-                          const double* __restrict__ Ubar, const R* __restrict__ A_in, const R* __restrict__ dA_in,
-                          const R* __restrict__ e_in, const R* __restrict__ abar, double* __restrict__ partial) {
+k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const int64_t* __restrict__ soff,
+                          const int* __restrict__ atom_struct, int Na, const int64_t* __restrict__ row,
+                          const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
+                          const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ A_in,
+                          const R* __restrict__ dA_in, const R* __restrict__ e_in, const R* __restrict__ abar,
+                          double* __restrict__ partial) {
     constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L, D = Sh::D;
     constexpr CgRowsGeom GM = cg_rows_geom(1, NA, KA, LM, int(sizeof(R)), ROWS);
     constexpr int S = GM.S, TEAMS = GM.teams, VEC = GM.vec, KAP = GM.kap, SLOT = GM.slot, TSTRIDE = GM.tstride;
@@ -1152,19 +1153,46 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ types, const in
     const CgRowsGeom gm = cg_rows_geom(T, NA, KA, LM, int(sizeof(R)), ROWS);
     const int nw = blockDim.x / 64, wave = threadIdx.x / 64, wl = threadIdx.x % 64;
     unsigned char* wbase = smem_raw + size_t(wave) * gm.wave_bytes;
+    // the wavefront's accumulator for its current species a: G[b][n][k]
     R* G = reinterpret_cast<R*>(wbase);
-    const int G_len = T * T * NA * KA;
+    const int G_len = T * NA * KA;
     for (int x = wl; x < G_len; x += 64) G[x] = R(0);
     const int team = wl / S, lane = wl % S;
     const bool in_team = team < TEAMS;
     R* myslots = reinterpret_cast<R*>(wbase + gm.off_slots) + (in_team ? team : 0) * TSTRIDE;
     int* tab = reinterpret_cast<int*>(wbase + gm.off_tab) + (in_team ? team : 0) * (2 * T + 1);
     const R rcA = R(dm.rcA), irA = R(1.0 / dm.rcA);
-    const int tiles = (Na + TEAMS - 1) / TEAMS;
-    for (int tile = blockIdx.x * nw + wave; tile < tiles; tile += gridDim.x * nw) {
-        const int i = tile * TEAMS + team;
-        const bool live = in_team && i < Na;
-        const int a = live ? types[i] : 0;
+    // tiles of TEAMS atoms of one species from the species-sorted list; each
+    // wavefront walks one contiguous range of them (so it meets each species in
+    // one run) and owns partial row gw, whose section for species a it writes
+    // when its run of species a ends; sections it never meets are zero
+    const int gw = blockIdx.x * nw + wave, GW = gridDim.x * nw;
+    const int tiles_ub = (Na + TEAMS - 1) / TEAMS + T;
+    const int per_wave = (tiles_ub + GW - 1) / GW;
+    double* __restrict__ prow = partial + (long)gw * T * G_len;
+    unsigned met = 0;  // species whose section this wavefront has written
+    int cur_a = -1;
+    auto flush_species = [&]() {
+        if (cur_a < 0) return;
+        X::wave_fence();
+        for (int x = wl; x < G_len; x += 64) {
+            prow[(long)cur_a * G_len + x] = double(G[x]);
+            G[x] = R(0);
+        }
+        met |= 1u << cur_a;
+        X::wave_fence();
+    };
+    for (int tile = gw * per_wave; tile < (gw + 1) * per_wave && tile < tiles_ub; ++tile) {
+        int a;
+        long lo = 0, hi = 0;
+        species_chunk(soff, T, TEAMS, tile, &a, &lo, &hi);
+        if (a < 0) break;
+        if (a != cur_a) {
+            flush_species();
+            cur_a = a;
+        }
+        const bool live = in_team && lo + team < hi;
+        const int i = live ? order[lo + team] : 0;
         const int s = live ? atom_struct[i] : 0;
         const int64_t p0 = live ? row[i] : 0;
         R ui[3], U[9];
@@ -1228,7 +1256,7 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ types, const in
             for (int r = 0; r < ROWS; ++r) {
                 const int n = lane * ROWS + r;
                 if (n >= NA) continue;
-                R* g = G + ((a * T + cur_b) * NA + n) * KA;
+                R* g = G + (cur_b * NA + n) * KA;
 #pragma unroll
                 for (int k = 0; k < KA; ++k) {
                     __hip_atomic_fetch_add(g + k, acc[r][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1332,13 +1360,10 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ types, const in
         flush();
         X::wave_fence();
     }
-    __syncthreads();
-    for (int x = threadIdx.x; x < G_len; x += blockDim.x) {
-        double sum = 0.0;
-        for (int w = 0; w < nw; ++w)
-            sum += double(reinterpret_cast<const R*>(smem_raw + size_t(w) * gm.wave_bytes)[x]);
-        partial[(long)blockIdx.x * G_len + x] = sum;
-    }
+    flush_species();
+    for (int t = 0; t < T; ++t)
+        if (!(met >> t & 1u))
+            for (int x = wl; x < G_len; x += 64) prow[(long)t * G_len + x] = 0.0;
 }
 
 // ------------------------------------------ network and radial coefficient grad

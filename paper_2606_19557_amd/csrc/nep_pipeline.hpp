@@ -118,6 +118,7 @@ nep_status run_shape(const Ctx& c) {
                        c.Ns, c.Na, c.dE, static_cast<const R*>(c.dF), c.dW, Wd(L.ebar), Wd(L.Ubar), Wr(L.ubar));
     }
 
+    int ang_rows_used = L.ang_rows;  // partial rows the coefficient sweep writes
     if (Na > 0) {
         if ((rs = with_team(c.plan.team_tangent, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
@@ -149,12 +150,20 @@ nep_status run_shape(const Ctx& c) {
             else if ((rs = with_cg_rows<nep_status>(c.plan.cg_rows, [&](auto R_) -> nep_status {
                     constexpr int ROWS = decltype(R_)::value;
                     const size_t shm = size_t(cg_rows_nw) * cg_rows_gm.wave_bytes;
+                    const void* kfn = reinterpret_cast<const void*>(&k_angular_coeff_grad_rows<R, Sh, ROWS>);
                     if (shm > 64 * 1024)
-                        NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular_coeff_grad_rows<R, Sh, ROWS>),
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
-                    NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad_rows<R, Sh, ROWS>), dim3(L.ang_rows),
-                               dim3(64 * cg_rows_nw), shm, st, dm, c.types, c.atom_struct, Na, c.row, c.seg, pairs,
-                               Wr(L.ubar), Wd(L.Ubar), Wr(L.A), Wr(L.dA), Wr(L.e), Wr(L.abar), Wd(L.ang_part));
+                        NEP_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
+                    // each wavefront walks a fixed range of tiles, so the grid is
+                    // the number of blocks the GPU holds at once (no second round),
+                    // at most the plan's partial rows
+                    const int resident = resident_blocks(kfn, 64 * cg_rows_nw, shm);
+                    if (resident < 0) return fail(NEP_ERR_HIP, "occupancy query of the coefficient sweep failed");
+                    const int grid = std::max(1, std::min(L.ang_rows / cg_rows_nw, resident));
+                    ang_rows_used = grid * cg_rows_nw;
+                    NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad_rows<R, Sh, ROWS>),
+                               dim3(grid), dim3(64 * cg_rows_nw), shm, st, dm, c.species_order,
+                               c.species_offset, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
+                               Wr(L.A), Wr(L.dA), Wr(L.e), Wr(L.abar), Wd(L.ang_part));
                     return NEP_OK;
                 })))
                 return rs;
@@ -190,7 +199,7 @@ nep_status run_shape(const Ctx& c) {
     }
     if (Na > 0 && dm.offB1 > 0)
         NEP_LAUNCH("reduce_stage", k_reduce_stage<kRedBlock / 64>, dim3(int((dm.offB1 + 63) / 64), kStageGroups), dim3(kRedBlock), 0,
-                   st, dm, Sh::NR * Sh::KR, Wd(L.outer_part), L.outer_rows, Wd(L.ang_part), L.ang_rows, Wd(L.stage),
+                   st, dm, Sh::NR * Sh::KR, Wd(L.outer_part), L.outer_rows, Wd(L.ang_part), ang_rows_used, Wd(L.stage),
                    c.species_offset, L.outer_chunk);
     NEP_LAUNCH("final_reduce", (k_final_reduce<R>), dim3(int((dm.offB1 + kRedBlock) / kRedBlock)), dim3(kRedBlock), 0,
                st, dm, c.Ns, c.atom_offset, Wd(L.stage), Na > 0 ? kStageGroups : 0, Wd(L.ebar), Wd(L.lossp), c.lam_e,
