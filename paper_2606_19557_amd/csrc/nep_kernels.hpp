@@ -619,17 +619,21 @@ __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __
 // B = dE_i/dA in LDS from the stored moments and e, then runs force_pass.
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
-k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ types, int Na,
-        const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
+k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ order, const int64_t* __restrict__ soff,
+        int Na, const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
         const int* __restrict__ reverse, const R* __restrict__ A_in, const R* __restrict__ e_in,
         Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
     constexpr int NA = Sh::NA, LM = Sh::LM, D = Sh::D;
     constexpr int TEAMS = kBlock / S;
     __shared__ R Bsh[TEAMS][NA * LM];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * TEAMS + team;
-    const bool live = i < Na;
-    const int a = live ? types[i] : 0;
+    // one species per block (uniform coefficient addresses), as in the sweeps
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, dm.T, TEAMS, xcd_tile(blockIdx.x, gridDim.x), &a, &lo, &hi);
+    if (a < 0) return;
+    const bool live = lo + team < hi;
+    const int i = live ? order[lo + team] : 0;
     const R* __restrict__ ei = e_in + (long)(live ? i : 0) * D;
     if (live) {
         moment_adjoints<R, Sh, S, false>(lane, A_in + (long)i * NA * LM, nullptr, ei, nullptr, Bsh[team], nullptr);

@@ -98,9 +98,9 @@ nep_status run_shape(const Ctx& c) {
         if (Na > 0 && (rs = with_team(c.plan.team_force, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
                 if (!fused_force)
-                    NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, dm, theta,
-                               c.types, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A), Wr(L.e), hslots, Wr(L.Fown),
-                               Wr(L.Wat));
+                    NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st, dm,
+                               theta, c.species_order, c.species_offset, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A),
+                               Wr(L.e), hslots, Wr(L.Fown), Wr(L.Wat));
                 NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, Na,
                            c.row, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
                 return NEP_OK;
