@@ -1410,14 +1410,16 @@ struct OuterMma : Mfma<R> {
 //   W0[mu][nu] = sum_i alpha_mu (s q)_nu + beta_mu (s dq)_nu     (matrix cores),
 //   b0[mu] = -sum_i alpha_mu, w1[mu] = sum_i gamma_mu,
 //   c_R[a][b][n][k] = sum_i abar_n S0[b][k] + e_n S1[b][k]        (matrix cores).
-// The block walks its chunk in sub-chunks of SC atoms: every operand row of a
+// The block walks its chunk in sub-chunks of SC atoms (32 in FP32 when their
+// operand rows fit 64 KB of LDS, else 16, so that rows of wide networks and
+// many species still leave room for several blocks per CU): every operand row of a
 // sub-chunk is copied once into LDS with coalesced loads (rows of the
 // per-unit arrays are contiguous in the species-sorted list), then each wave
 // updates the 32 x 32 (16 x 16 in FP64) output tiles it owns from LDS. A tile
 // belongs to one wave for the whole chunk, so its sums need no cross-wave step.
-template <typename R>
+template <typename R, int SC_ = 16>
 struct OuterTiles {
-    static constexpr int SC = sizeof(R) == 4 ? 32 : 16;  // atoms per staged sub-chunk
+    static constexpr int SC = SC_;  // atoms per staged sub-chunk
     static constexpr int MAXTW = 6;                        // tiles per wave at most
     // accumulator slots the kernel is built with for a network: the smallest
     // of 1, 2, 4, 6 covering its tiles (fewer slots, fewer registers)
@@ -1436,7 +1438,7 @@ struct OuterTiles {
     }
 };
 
-template <typename R, class Sh, int MAXTW>
+template <typename R, class Sh, int MAXTW, int SCA>
 __global__ void __launch_bounds__(kBlock)
 k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict__ order,
              const int64_t* __restrict__ soff, int chunk, const R* __restrict__ q_in, const R* __restrict__ dq_in,
@@ -1444,7 +1446,7 @@ k_outer_grad(const Dims dm, const R* __restrict__ qscale, const int* __restrict_
              const R* __restrict__ beta, const R* __restrict__ gam, const R* __restrict__ S0,
              const R* __restrict__ S1, int units_by_atom, double* __restrict__ partial) {
     using MM = OuterMma<R>;
-    using OT = OuterTiles<R>;
+    using OT = OuterTiles<R, SCA>;
     constexpr int M = MM::M, NR = Sh::NR, KR = Sh::KR, D = Sh::D, SC = OT::SC;
     constexpr int WAVES = OT::WAVES, KSTEPS = 2 * SC / MM::KPI;
     extern __shared__ __align__(16) unsigned char outer_smem[];

@@ -178,16 +178,26 @@ nep_status run_shape(const Ctx& c) {
                 return NEP_OK;
             })))
             return rs;
-        const size_t og_shm = OuterTiles<R>::lds_bytes(dm);
-        auto outer = [&](auto TW_) -> nep_status {
-            constexpr int TW = decltype(TW_)::value;
+        // FP32 sub-chunks of 32 atoms (half the barrier rounds of 16) unless a
+        // 32-atom block's LDS (> 32 KB) would cut the blocks per CU of a grid
+        // with work for several of them (>= 1024 blocks); FP64 takes 16
+        const size_t lds32 = OuterTiles<R, 32>::lds_bytes(dm);
+        const bool sc32 = sizeof(R) == 4 && lds32 <= 64 * 1024 && (lds32 <= 32 * 1024 || L.outer_rows < 1024);
+        const size_t og_shm = sc32 ? OuterTiles<R, 32>::lds_bytes(dm) : OuterTiles<R, 16>::lds_bytes(dm);
+        auto outer_sc = [&](auto TW_, auto SC_) -> nep_status {
+            constexpr int TW = decltype(TW_)::value, SC = decltype(SC_)::value;
             if (og_shm > 64 * 1024)
-                NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_outer_grad<R, Sh, TW>),
+                NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_outer_grad<R, Sh, TW, SC>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(og_shm)));
-            NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh, TW>), dim3(L.outer_rows), dim3(kBlock), og_shm, st, dm,
+            NEP_LAUNCH("outer_grad", (k_outer_grad<R, Sh, TW, SC>), dim3(L.outer_rows), dim3(kBlock), og_shm, st, dm,
                        qscale, c.species_order, c.species_offset, L.outer_chunk, q, Wr(L.dq), Wr(L.abar), Wr(L.e),
                        Wr(L.alpha), Wr(L.beta), Wr(L.gam), Wr(L.S0), Wr(L.S1), fused ? 1 : 0, Wd(L.outer_part));
             return NEP_OK;
+        };
+        auto outer = [&](auto TW_) -> nep_status {
+            if constexpr (sizeof(R) == 4)
+                if (sc32) return outer_sc(TW_, std::integral_constant<int, 32>{});
+            return outer_sc(TW_, std::integral_constant<int, 16>{});
         };
         switch (OuterTiles<R>::tiles_per_wave(dm)) {
             case 1: rs = outer(std::integral_constant<int, 1>{}); break;
