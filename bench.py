@@ -477,11 +477,14 @@ def main():
         fl, by = work
         sec = avg_ms * 1e-3
         traffic = measured_traffic(name, args.workload, used_plan)
-        # the bound: FLOP time at the vector peak against the time to move the
-        # kernel's bytes at the HBM peak -- the measured HBM bytes when a
-        # counter summary of these sources exists, else the algorithmic bytes
+        # the bound: the kernel's algorithmic FLOPs at the vector peak against
+        # its algorithmic bytes at the HBM peak (the work model's FLOP/byte
+        # against the ridge); the measured HBM bytes, when a counter summary of
+        # these sources exists, are reported beside it (traffic and
+        # hbm_frac_measured) -- bytes above the algorithmic ones are re-reads
+        # and partial-line writes, not the method's work
         t_alu = fl / (peak_alu * 1e12)
-        t_hbm = (traffic if traffic is not None else by) / (PEAK_HBM_GBS * 1e9)
+        t_hbm = by / (PEAK_HBM_GBS * 1e9)
         if t_alu >= t_hbm:
             achieved, peak = fl / sec / 1e12, peak_alu
             roof = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
