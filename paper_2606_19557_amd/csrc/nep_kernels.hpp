@@ -1196,36 +1196,46 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
             cur_a = a;
         }
         const bool live = in_team && lo + team < hi;
-        const int i = live ? order[lo + team] : 0;
-        const int s = live ? atom_struct[i] : 0;
-        const int64_t p0 = live ? row[i] : 0;
+        // The atom's data: every lane loads (a lane without an atom reads the
+        // tile's first one, lo < hi, and drops what it read), so that the loads
+        // go out together rather than one after another behind branches.
+        const int i = order[live ? lo + team : lo];
+        const int s = atom_struct[i];
+        const int64_t p0 = row[i];
         R ui[3], U[9];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ui[d] = live ? ubar[(long)i * 3 + d] : R(0);
+        for (int d = 0; d < 3; ++d) ui[d] = ubar[(long)i * 3 + d];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
+        for (int c = 0; c < 9; ++c) U[c] = R(Ubar[(long)s * 9 + c]);
         if (live && lane == 0) {
+            const int2* __restrict__ sg = reinterpret_cast<const int2*>(seg) + (long)i * T;
+            int2 v[kMaxTypes];
+#pragma unroll
+            for (int b = 0; b < kMaxTypes; ++b) v[b] = sg[b < T ? b : T - 1];
             int cum = 0, pos = 0;
-            for (int b = 0; b < T; ++b) {
-                const int tot = seg[(i * T + b) * 2], ang = seg[(i * T + b) * 2 + 1];
+#pragma unroll
+            for (int b = 0; b < kMaxTypes; ++b) {
+                if (b >= T) break;
                 tab[b] = cum;
                 tab[T + 1 + b] = pos;
-                cum += ang;
-                pos += tot;
+                cum += v[b].y;
+                pos += v[b].x;
             }
             tab[T] = cum;
         }
-        // this lane's rows of the atom's moment adjoints
+        // this lane's rows of the atom's moment adjoints (rows past N_A and
+        // lanes without an atom load row N_A - 1 and keep zeros)
         R Q[ROWS][LM], Bp[ROWS][LM];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int n = lane * ROWS + r;
-            if (live && n < NA) {
-                row_adjoints<R, Sh>(n, A_in + (long)i * NA * LM, dA_in + (long)i * NA * LM, e_in + (long)i * D,
-                                    abar + (long)i * D, Q[r], Bp[r]);
-            } else {
+            const bool own = live && n < NA;
+            row_adjoints<R, Sh>(n < NA ? n : NA - 1, A_in + (long)i * NA * LM, dA_in + (long)i * NA * LM,
+                                e_in + (long)i * D, abar + (long)i * D, Q[r], Bp[r]);
 #pragma unroll
-                for (int lm = 0; lm < LM; ++lm) Q[r][lm] = Bp[r][lm] = R(0);
+            for (int lm = 0; lm < LM; ++lm) {
+                Q[r][lm] = own ? Q[r][lm] : R(0);
+                Bp[r][lm] = own ? Bp[r][lm] : R(0);
             }
         }
         X::wave_fence();
@@ -1271,11 +1281,16 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
         while (cA.b < T) {
             // loads for the next batches: the records of t+2, then the
             // neighbours' seeds of t+1 (issued last, so that waiting for them
-            // at the next batch does not also wait for the records)
-            const Rec<R> recC = fetch(cC);
-            R ujB[3] = {R(0), R(0), R(0)};
-            if (cB.b < T && cB.kin + lane < cB.ang) {
-                const long j = rec_j(recB);
+            // at the next batch does not also wait for the records). Both are
+            // issued by every lane of the loop, a lane past its segment's end
+            // reading the atom's first pair and atom 0 (both exist for an atom
+            // with angular pairs) and never using what it read: with no
+            // branch around them the compiler waits for exactly the loads a
+            // value needs instead of all of them.
+            const Rec<R> recC = pairs[cC.b < T && cC.kin + lane < cC.ang ? p0 + cC.pos + cC.kin + lane : p0];
+            R ujB[3];
+            {
+                const long j = cB.b < T && cB.kin + lane < cB.ang ? long(rec_j(recB)) : 0L;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ujB[d] = ubar[j * 3 + d];
             }

@@ -104,3 +104,41 @@ def test_missing_key_and_size_mismatch_rejected(tmp_path):
     P, D = io.num_params(md)
     with pytest.raises(ValueError):
         io.save_model(str(tmp_path / "x.txt"), md, ["C"], np.zeros(P - 1), np.ones(D))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_reloaded_model_gives_identical_gpu_predictions(tmp_path, dtype):
+    """Save, load, and evaluate on the GPU: E, F, W bitwise those of the
+    parameters before saving (the round trip is exact, so the kernels see the
+    same bits)."""
+    import torch
+
+    import paper_2606_19557_amd as N
+    from helpers import SMALL_ALLOY, device_inputs, small_alloy_batch
+
+    md = dict(SMALL_ALLOY)
+    m = O.Model(**md)
+    P, D = O.dims(m)
+    b = small_alloy_batch(n_struct=3)
+    theta = draw_theta(P, 13)
+    s = O.scaler(O.descriptors(m, theta, b))
+    b, theta, s, _ = device_inputs(dtype, b, theta, s)
+    npt = np.float32 if dtype == "f32" else np.float64
+    path = str(tmp_path / "m.txt")
+    io.save_model(path, md, ["A", "B", "C"], theta.astype(npt), s.astype(npt), dtype=dtype)
+    inp, gd, th2, s2 = io.load_model(path)
+    assert gd == dtype
+    model = N.Model.from_dict(md, dtype=dtype)
+    td = model.torch_dtype
+    gb = N.Batch.from_host(b, dtype=td)
+    nb = N.nep_build_neighbors(model, gb)
+    ws = N.workspace(model, gb, nb)
+    outs = []
+    for th, qs in ((theta, s), (th2, s2)):
+        E, F, W = N.nep_forward(N.Model.from_dict(inp.model if th is th2 else md, dtype=dtype),
+                                torch.tensor(np.asarray(th, dtype=npt), device="cuda"),
+                                torch.tensor(np.asarray(qs, dtype=npt), device="cuda"), gb, nb, ws)
+        outs.append((E.cpu(), F.cpu(), W.cpu()))
+    for a, c in zip(*outs):
+        assert torch.equal(a, c)
