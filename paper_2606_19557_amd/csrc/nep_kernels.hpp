@@ -523,7 +523,9 @@ __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __
             }
         }
         const R* __restrict__ cA = theta + dm.offA + (long)((a * T + b) * NA) * KA;
-        // the next record and reverse index are loaded one iteration ahead
+        // the next record and reverse index are loaded one iteration ahead,
+        // with no branch around the loads (the last iteration reads the
+        // segment's last pair again and drops it)
         Rec<R> nx{};
         int nrev = -1;
         if (lane < tot) {
@@ -533,9 +535,10 @@ __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __
         for (int k = lane; k < tot; k += S) {
             const Rec<R> pr = nx;
             const int q = nrev;
-            if (k + S < tot) {
-                nx = pairs[p + k + S];
-                nrev = reverse[p + k + S];
+            {
+                const int kn = min(k + S, tot - 1);
+                nx = pairs[p + kn];
+                nrev = reverse[p + kn];
             }
             const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
             const R ir = R(1) / r;
@@ -727,20 +730,23 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ or
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) Sb[kk] = R(0);
         // the next batch's record is loaded one batch ahead; the neighbour's
-        // seed (a dependent load) is issued before the basis is evaluated
+        // seed (a dependent load) is issued before the basis is evaluated.
+        // Inside the loop no branch guards a load (a lane past the segment's
+        // end reads its last pair, or atom 0's seed, and drops the values), so
+        // the compiler waits only for the loads a value needs.
         Rec<R> nx{};
         if (lane < tot) nx = pairs[p + lane];
         for (int base = 0; base < tot; base += S) {
             const int k = base + lane;
             const bool angb = base < ang;  // team-uniform: this batch starts inside the angular prefix
             const Rec<R> pr = nx;
-            R uj[3] = {R(0), R(0), R(0)};
-            if (k < tot) {
+            R uj[3];
+            {
                 const long j = rec_j(pr);
 #pragma unroll
                 for (int be = 0; be < 3; ++be) uj[be] = ubar[j * 3 + be];
             }
-            if (k + S < tot) nx = pairs[p + k + S];
+            nx = pairs[p + min(k + S, tot - 1)];
             R gpv[NA], g[NA], Y[LM], vdY[LM];
 #pragma unroll
             for (int n = 0; n < NA; ++n) gpv[n] = g[n] = R(0);
@@ -965,19 +971,20 @@ k_angular_coeff_grad(const Dims dm, const int* __restrict__ types, const int* __
             for (int n = 0; n < NA; ++n)
 #pragma unroll
                 for (int o = 0; o < OWN; ++o) acc[n][o] = R(0);
-            // record one batch ahead; the neighbour's seed before the basis
+            // record one batch ahead; the neighbour's seed before the basis; no
+            // branch guards a load inside the loop (as in the tangent sweep)
             Rec<R> nx{};
             if (lane < ang) nx = pairs[p + lane];
             for (int base = 0; base < ang; base += S) {
                 const int k = base + lane;
                 const Rec<R> pr = nx;
-                R uj[3] = {R(0), R(0), R(0)};
-                if (k < ang) {
+                R uj[3];
+                {
                     const long j = rec_j(pr);
 #pragma unroll
                     for (int be = 0; be < 3; ++be) uj[be] = ubar[j * 3 + be];
                 }
-                if (k + S < ang) nx = pairs[p + k + S];
+                nx = pairs[p + min(k + S, ang - 1)];
                 R P[NA], Rn[NA], fa[KA], fap[KA];
 #pragma unroll
                 for (int n = 0; n < NA; ++n) P[n] = Rn[n] = R(0);
