@@ -434,24 +434,71 @@ struct MomentExchange {
 // atom species, the slots, and per team the segment table (angular starts
 // [T+1], row offsets [T]). Host and device use the same function.
 struct CgRowsGeom {
-    int S, teams, vec, kap, slot, tstride;
+    int S, teams, vec, kfp, slot, tstride;
     size_t off_slots, off_tab, wave_bytes;
 };
-__host__ __device__ constexpr CgRowsGeom cg_rows_geom(int T, int NA, int KA, int LM, int rbytes, int rows) {
+// Bank-conflict count of one wavefront's 16-byte LDS accesses to the slots:
+// lane (team t, lane q) writes its own slot at t*ts + q*slot and every lane
+// of team t reads one slot of its team, chunk by chunk (all sizes in 4-byte
+// words). Lanes are served `group` at a time by `banks` banks; a group costs
+// the largest number of distinct 16-byte addresses that share a bank quad.
+__host__ __device__ constexpr int cg_slot_conflicts(int S, int slot_w, int ts_w, int banks, int group) {
+    const int teams = 64 / S, quads = banks / 4;
+    int cost = 0;
+    for (int c = 0; c < slot_w; c += 4)
+        for (int g0 = 0; g0 < 64; g0 += group) {
+            int wq[16] = {}, rq[16] = {}, last_t = -1;
+            for (int l = g0; l < g0 + group && l < teams * S; ++l) {
+                const int t = l / S, q = l % S;
+                ++wq[((t * ts_w + q * slot_w + c) / 4) % quads];
+                if (t != last_t) ++rq[((t * ts_w + c) / 4) % quads];  // one address per team
+                last_t = t;
+            }
+            int mw = 0, mr = 0;
+            for (int b = 0; b < quads; ++b) {
+                mw = wq[b] > mw ? wq[b] : mw;
+                mr = rq[b] > mr ? rq[b] : mr;
+            }
+            cost += mw + mr;
+        }
+    return cost;
+}
+// LDS layout of the row-owned angular coefficient sweep (one region per
+// wavefront): G [T][N_A][K_A]; a slot per lane holding one pair's Y [24],
+// (v.grad) Y [24] and the interleaved (f_k, (v.r^) f'_k) pairs, padded to
+// whole 16-byte vectors; the team stride padded by whole vectors to the
+// fewest bank conflicts for 8-lane groups on 32 banks and 16-lane groups on
+// 64 banks; then the teams' segment tables. cg_rows_slots fixes the slots
+// (no dependence on T: kernels take it as a compile-time constant, the
+// search never runs on the device), cg_rows_place the offsets for T species.
+__host__ __device__ constexpr CgRowsGeom cg_rows_slots(int NA, int KA, int LM, int rbytes, int rows) {
     CgRowsGeom g{};
     g.S = (NA + rows - 1) / rows;
     g.teams = 64 / g.S;
     g.vec = 16 / rbytes;
-    g.kap = (KA + g.vec - 1) / g.vec * g.vec;
-    g.slot = 2 * LM + 2 * g.kap;
-    const int tw = g.S * g.slot * rbytes / 4;
-    const int tsw = tw + ((4 - tw) % 32 + 32) % 32;
-    g.tstride = tsw * 4 / rbytes;
+    g.kfp = (2 * KA + g.vec - 1) / g.vec * g.vec;
+    g.slot = 2 * LM + g.kfp;
+    const int sw = g.slot * rbytes / 4;
+    int best = -1, best_pad = 0;
+    for (int pad = 0; pad < 32; pad += 4) {
+        const int c = cg_slot_conflicts(g.S, sw, g.S * sw + pad, 32, 8) + cg_slot_conflicts(g.S, sw, g.S * sw + pad, 64, 16);
+        if (best < 0 || c < best) {
+            best = c;
+            best_pad = pad;
+        }
+    }
+    g.tstride = (g.S * sw + best_pad) * 4 / rbytes;
+    return g;
+}
+__host__ __device__ constexpr CgRowsGeom cg_rows_place(CgRowsGeom g, int T, int NA, int KA, int rbytes) {
     const size_t G = size_t(T) * NA * KA * rbytes;
     g.off_slots = (G + 15) / 16 * 16;
     g.off_tab = g.off_slots + size_t(g.teams) * g.tstride * rbytes;
     g.wave_bytes = (g.off_tab + size_t(g.teams) * (2 * T + 1) * 4 + 15) / 16 * 16;
     return g;
+}
+__host__ __device__ constexpr CgRowsGeom cg_rows_geom(int T, int NA, int KA, int LM, int rbytes, int rows) {
+    return cg_rows_place(cg_rows_slots(NA, KA, LM, rbytes, rows), T, NA, KA, rbytes);
 }
 // Wavefronts per block of that sweep: four, two or one, the most that still
 // lets a CU's 160 KB of LDS hold as many wavefronts as single-wavefront blocks

@@ -1154,14 +1154,15 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                           const R* __restrict__ dA_in, const R* __restrict__ e_in, const R* __restrict__ abar,
                           double* __restrict__ partial) {
     constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L, D = Sh::D;
-    constexpr CgRowsGeom GM = cg_rows_geom(1, NA, KA, LM, int(sizeof(R)), ROWS);
-    constexpr int S = GM.S, TEAMS = GM.teams, VEC = GM.vec, KAP = GM.kap, SLOT = GM.slot, TSTRIDE = GM.tstride;
-    static_assert(LM % VEC == 0 && KAP % VEC == 0 && SLOT % VEC == 0 && TSTRIDE % VEC == 0, "vector layout");
+    constexpr CgRowsGeom GM = cg_rows_slots(NA, KA, LM, int(sizeof(R)), ROWS);
+    constexpr int S = GM.S, TEAMS = GM.teams, VEC = GM.vec, KFP = GM.kfp, SLOT = GM.slot, TSTRIDE = GM.tstride;
+    static_assert(LM % VEC == 0 && KFP % VEC == 0 && SLOT % VEC == 0 && TSTRIDE % VEC == 0 && VEC % 2 == 0,
+                  "vector layout");
     using V = typename VecOf<R>::type;
     using X = MomentExchange<R, NA, LM, S>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = dm.T;
-    const CgRowsGeom gm = cg_rows_geom(T, NA, KA, LM, int(sizeof(R)), ROWS);
+    const CgRowsGeom gm = cg_rows_place(GM, T, NA, KA, int(sizeof(R)));
     const int nw = blockDim.x / 64, wave = threadIdx.x / 64, wl = threadIdx.x % 64;
     unsigned char* wbase = smem_raw + size_t(wave) * gm.wave_bytes;
     // the wavefront's accumulator for its current species a: G[b][n][k]
@@ -1222,11 +1223,12 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
             int cum = 0, pos = 0;
 #pragma unroll
             for (int b = 0; b < kMaxTypes; ++b) {
-                if (b >= T) break;
-                tab[b] = cum;
-                tab[T + 1 + b] = pos;
-                cum += v[b].y;
-                pos += v[b].x;
+                if (b < T) {
+                    tab[b] = cum;
+                    tab[T + 1 + b] = pos;
+                    cum += v[b].y;
+                    pos += v[b].x;
+                }
             }
             tab[T] = cum;
         }
@@ -1315,23 +1317,36 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                 const R vu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
                 // each value goes to the slot as soon as it is known, which keeps
                 // the basis and the harmonics from being live at once
-                R* sl = myslots + lane * SLOT;
+                // (whole 16-byte vectors: one LDS write per vector)
+                V* sl = reinterpret_cast<V*>(myslots + lane * SLOT);
                 {
                     R fa[KA], fap[KA];
                     cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
 #pragma unroll
-                    for (int k = 0; k < KAP; ++k) {
-                        sl[2 * LM + k] = k < KA ? fa[k] : R(0);
-                        sl[2 * LM + KAP + k] = k < KA ? fap[k] * vu : R(0);
+                    for (int c = 0; c < KFP / VEC; ++c) {
+                        V w;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const int x = c * VEC + e, k = x / 2;
+                            w[e] = k < KA ? ((x & 1) ? fap[k] * vu : fa[k]) : R(0);
+                        }
+                        sl[2 * LM / VEC + c] = w;
                     }
                 }
                 const D1<R> dx = {u[0], v[0]}, dy = {u[1], v[1]}, dz = {u[2], v[2]};
                 D1<R> Yd[LM];
                 solid_harmonics<D1<R>, R, L>(dx, dy, dz, Yd);
 #pragma unroll
-                for (int lm = 0; lm < LM; ++lm) {
-                    sl[lm] = Yd[lm].v;
-                    sl[LM + lm] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
+                for (int c = 0; c < LM / VEC; ++c) {
+                    V y, dv;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int lm = c * VEC + e;
+                        y[e] = Yd[lm].v;
+                        dv[e] = (Yd[lm].d - R(lm_degree<LM>(lm)) * Yd[lm].v * vu) * ir;
+                    }
+                    sl[c] = y;
+                    sl[LM / VEC + c] = dv;
                 }
             }
             X::wave_fence();
@@ -1360,16 +1375,16 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                         }
                 }
 #pragma unroll
-                for (int c = 0; c < KAP / VEC; ++c) {
-                    const V f = sl[2 * LM / VEC + c], fp = sl[2 * LM / VEC + KAP / VEC + c];
+                for (int c = 0; c < KFP / VEC; ++c) {
+                    const V w = sl[2 * LM / VEC + c];  // (f_k, (v.r^) f'_k) pairs
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        const int k = c * VEC + e;
+                    for (int e = 0; e < VEC; e += 2) {
+                        const int k = (c * VEC + e) / 2;
                         if (k >= KA) continue;
 #pragma unroll
                         for (int r = 0; r < ROWS; ++r) {
-                            acc[r][k] += pn[r] * f[e];
-                            acc[r][k] += rn[r] * fp[e];
+                            acc[r][k] += pn[r] * w[e];
+                            acc[r][k] += rn[r] * w[e + 1];
                         }
                     }
                 }
