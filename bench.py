@@ -309,14 +309,17 @@ def main():
     # neighbour lists, built once (timed separately)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nb = N.nep_build_neighbors(model, gb, capacity=host.num_atoms * 80)
+    # (a minibatch workload's dataset lists also keep each structure's species
+    # runs, from which a minibatch's species order is gathered)
+    runs = w.minibatch > 0
+    nb = N.nep_build_neighbors(model, gb, capacity=host.num_atoms * 80, species_runs=runs)
     torch.cuda.synchronize()
     nbr_first_ms = (time.perf_counter() - t0) * 1e3
     # again, warm (code objects loaded, buffers cached): the cost of a rebuild,
     # e.g. per step of a forward-only MD loop
     nbw_ws = N.workspace(model, gb)
     t0 = time.perf_counter()
-    nb = N.nep_build_neighbors(model, gb, capacity=nb.num_pairs, ws=nbw_ws)
+    nb = N.nep_build_neighbors(model, gb, capacity=nb.num_pairs, ws=nbw_ws, species_runs=runs)
     torch.cuda.synchronize()
     nbr_ms = (time.perf_counter() - t0) * 1e3
     del nbw_ws

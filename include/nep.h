@@ -134,6 +134,11 @@ typedef struct {
     int64_t num_pairs;        /* host, written by nep_build_neighbors (also on NEP_ERR_CAPACITY);
                                  at most 2^31 - 1 pairs per batch */
     int64_t num_angular_pairs;/* host, written by nep_build_neighbors */
+    int32_t* species_runs;    /* [Ns][T][2] or NULL: when set, nep_build_neighbors writes for each
+                                 structure s and species t the run {start, end} of s's species-t
+                                 atoms inside species_order ({0, 0} when s has none), and
+                                 nep_gather_batch on these lists gathers the minibatch's species
+                                 order from them instead of sorting it */
 } nep_neighbors;
 
 /* Reference data and loss weights, Eqs. (4)-(7). */
@@ -177,7 +182,8 @@ nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, n
  * structures ids[0..num_ids) of a packed dataset `src`, with their neighbour
  * lists (built once for the dataset) and targets, into a packed minibatch, in
  * the order given. Atoms, neighbour indices j and reverse-pair indices are
- * renumbered; the minibatch's species order is recomputed; energies, virials
+ * renumbered; the minibatch's species order is gathered from src_nbr->species_runs
+ * when the dataset's lists carry them, else sorted again; energies, virials
  * and has_virial (1 when the dataset has no mask) follow their structures.
  * ids is a device array; an id outside [0, src Ns) selects an empty structure.
  * The caller allocates the minibatch arrays: atom_offset [num_ids+1], cells
@@ -188,7 +194,9 @@ nep_status nep_build_neighbors(const nep_model* model, const nep_batch* batch, n
  * nbr->num_pairs and num_angular_pairs are left to the caller. Sizes that do
  * not match give wrong lists but no access outside the given arrays.
  * src_targets may be NULL (then energy, force, virial are not written); any of
- * energy, force, virial, has_virial may be NULL. ws: 8 (num_ids + 1) bytes. */
+ * energy, force, virial, has_virial may be NULL. ws: 8 (num_ids + 1) bytes, plus
+ * 4 T (num_ids + 1) when src_nbr->species_runs is set. nbr->species_runs is not
+ * written. */
 nep_status nep_gather_batch(const nep_model* model, const nep_batch* src, const nep_neighbors* src_nbr,
                             const nep_targets* src_targets, const int32_t* ids, int32_t num_ids, int64_t num_atoms,
                             int64_t* atom_offset, void* positions, int32_t* types, double* cells, nep_neighbors* nbr,

@@ -742,6 +742,23 @@ k_species_sort(long Na, int T, const int* __restrict__ types, int* __restrict__ 
     }
 }
 
+// Per structure s and species t of a batch, the run of s's atoms of species t
+// inside species_order: the stable sort keeps them together, in index order,
+// since a structure's atoms are one index range. runs[s][t] = {start, end},
+// zeroed beforehand so that a species absent from s has an empty run.
+// Species are valid here (checked before the launch), so order is a
+// permutation of the atoms.
+__global__ void __launch_bounds__(kNbBlock)
+k_species_runs(long Na, int T, const int* __restrict__ types, const int* __restrict__ atom_struct,
+               const int* __restrict__ order, const int64_t* __restrict__ soff, int* __restrict__ runs) {
+    const long p = (long)blockIdx.x * kNbBlock + threadIdx.x;
+    if (p >= Na) return;
+    const int i = order[p], t = types[i], s = atom_struct[i];
+    int* r = runs + 2L * s * T + 2 * t;
+    if (p == soff[t] || atom_struct[order[p - 1]] != s) r[0] = int(p);
+    if (p + 1 == soff[t + 1] || atom_struct[order[p + 1]] != s) r[1] = int(p + 1);
+}
+
 // ------------------------------------------------------------- minibatches
 
 // Per selected structure k (one block, chunked scan): atom and pair counts of
@@ -752,7 +769,8 @@ k_gather_structs(int n, const int* __restrict__ ids, int Ns, const int64_t* __re
                  const int64_t* __restrict__ src_row, const double* __restrict__ src_cells,
                  const double* __restrict__ src_E, const double* __restrict__ src_W, const uint8_t* __restrict__ src_hv,
                  int64_t* __restrict__ dst_off, int64_t* __restrict__ pair_base, double* __restrict__ dst_cells,
-                 double* __restrict__ dst_E, double* __restrict__ dst_W, uint8_t* __restrict__ dst_hv) {
+                 double* __restrict__ dst_E, double* __restrict__ dst_W, uint8_t* __restrict__ dst_hv, int T,
+                 const int* __restrict__ src_runs, int* __restrict__ run_base, int64_t* __restrict__ dst_soff) {
     __shared__ int64_t ba[kScanBlock], bp[kScanBlock];
     __shared__ int64_t carry_a, carry_p;
     if (threadIdx.x == 0) {
@@ -805,21 +823,87 @@ k_gather_structs(int n, const int* __restrict__ ids, int Ns, const int64_t* __re
         }
         __syncthreads();
     }
+    if (!src_runs) return;
+    // With the dataset's species runs: per species t, the exclusive scan over
+    // the selected structures of their runs' lengths, run_base[t][k] (and the
+    // species total in run_base[t][n]); the species offsets follow.
+    constexpr int WAVES = kScanBlock / 64;
+    __shared__ int wsum[WAVES];
+    __shared__ int carry_t[kMaxTypes];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (threadIdx.x < kMaxTypes) carry_t[threadIdx.x] = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += kScanBlock) {
+        const int k = base + threadIdx.x;
+        int sid = -1;
+        if (k < n) {
+            const int s = ids[k];
+            if (s >= 0 && s < Ns) sid = s;
+        }
+        for (int t = 0; t < T; ++t) {
+            const int c = sid >= 0 ? src_runs[2L * sid * T + 2 * t + 1] - src_runs[2L * sid * T + 2 * t] : 0;
+            int x = c;  // inclusive scan over the wavefront
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) wsum[wave] = x;
+            __syncthreads();
+            int pre = carry_t[t];
+            for (int w = 0; w < wave; ++w) pre += wsum[w];
+            if (k < n) run_base[(long)t * (n + 1) + k] = pre + x - c;
+            __syncthreads();
+            if (threadIdx.x == kScanBlock - 1) carry_t[t] = pre + x;
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        int64_t o = 0;
+        for (int t = 0; t < T; ++t) {
+            dst_soff[t] = o;
+            run_base[(long)t * (n + 1) + n] = carry_t[t];
+            o += carry_t[t];
+        }
+        dst_soff[T] = o;
+    }
 }
 
 // Per minibatch atom a < min(Na, dst_off[n]): position, species, per-species
 // pair counts, force target, structure index and row end.
 template <typename R>
-__global__ void __launch_bounds__(kNbBlock)
-k_gather_atoms(long Na, int n, int T, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
-               const int64_t* __restrict__ src_row, const R* __restrict__ src_pos, const int* __restrict__ src_types,
-               const int* __restrict__ src_seg, const R* __restrict__ src_F, const int64_t* __restrict__ dst_off,
-               const int64_t* __restrict__ pair_base, R* __restrict__ dst_pos, int* __restrict__ dst_types,
-               int* __restrict__ dst_seg, R* __restrict__ dst_F, int* __restrict__ dst_struct,
-               int64_t* __restrict__ dst_row) {
-    const long a = (long)blockIdx.x * kNbBlock + threadIdx.x;
+__device__ __forceinline__ void gather_atoms_block(
+    long blk, long Na, int n, int T, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
+    const int64_t* __restrict__ src_row, const R* __restrict__ src_pos, const int* __restrict__ src_types,
+    const int* __restrict__ src_seg, const R* __restrict__ src_F, const int64_t* __restrict__ dst_off,
+    const int64_t* __restrict__ pair_base, R* __restrict__ dst_pos, int* __restrict__ dst_types,
+    int* __restrict__ dst_seg, R* __restrict__ dst_F, int* __restrict__ dst_struct, int64_t* __restrict__ dst_row,
+    const int* __restrict__ src_runs, const int* __restrict__ src_order, const int* __restrict__ run_base,
+    const int64_t* __restrict__ dst_soff, int* __restrict__ dst_order) {
+    const long a = blk * kNbBlock + threadIdx.x;
     if (a == 0) dst_row[0] = 0;
     if (a >= Na || a >= dst_off[n]) return;
+    if (src_runs) {
+        // entry a of the minibatch's species order: species t and rank r in
+        // it, the structure k whose run holds rank r (the last k with
+        // run_base[t][k] <= r; run_base[t][n] is the total), then the atom
+        // that run holds in the dataset's species order, renumbered
+        int t = 0;
+        while (t + 1 < T && dst_soff[t + 1] <= a) ++t;
+        const int r = int(a - dst_soff[t]);
+        const int* __restrict__ bt = run_base + (long)t * (n + 1);
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bt[mid] <= r)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int sid = ids[lo];
+        const int src_atom = src_order[src_runs[2L * sid * T + 2 * t] + (r - bt[lo])];
+        dst_order[a] = int(dst_off[lo] + (src_atom - src_off[sid]));
+    }
     int lo = 0, hi = n;  // dst_off[lo] <= a < dst_off[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -845,13 +929,15 @@ k_gather_atoms(long Na, int n, int T, const int* __restrict__ ids, const int64_t
 // copied with j renumbered and the reverse index moved to the minibatch's
 // pair numbering.
 template <typename R>
-__global__ void __launch_bounds__(kNbBlock)
-k_gather_pairs(long P, int n, const int* __restrict__ ids, const int64_t* __restrict__ src_off,
-               const int64_t* __restrict__ src_row, const Rec<R>* __restrict__ src_pairs,
-               const int* __restrict__ src_rev, const int64_t* __restrict__ dst_off,
-               const int64_t* __restrict__ pair_base, Rec<R>* __restrict__ dst_pairs, int* __restrict__ dst_rev) {
+__device__ __forceinline__ void gather_pairs_block(long blk, long P, int n, const int* __restrict__ ids,
+                                                   const int64_t* __restrict__ src_off,
+                                                   const int64_t* __restrict__ src_row,
+                                                   const Rec<R>* __restrict__ src_pairs,
+                                                   const int* __restrict__ src_rev, const int64_t* __restrict__ dst_off,
+                                                   const int64_t* __restrict__ pair_base, Rec<R>* __restrict__ dst_pairs,
+                                                   int* __restrict__ dst_rev) {
     const long lim = min(P, (long)pair_base[n]);
-    const long p0 = (long)blockIdx.x * kNbBlock;
+    const long p0 = blk * kNbBlock;
     if (p0 >= lim) return;  // the whole block
     // the block's pairs lie in a short run of structures: two lanes bisect
     // pair_base for its first and last pair, every lane then bisects inside it
@@ -893,6 +979,30 @@ k_gather_pairs(long P, int n, const int* __restrict__ ids, const int64_t* __rest
     dst_rev[p] = rv < 0 ? -1 : int(rv - s0 + pair_base[k]);
 }
 
+// One launch for both copies: blocks below atom_blocks take atoms, the rest
+// take pairs (both need only the structure offsets and pair bases).
+template <typename R>
+__global__ void __launch_bounds__(kNbBlock)
+k_gather_atoms_pairs(long atom_blocks, long Na, int n, int T, const int* __restrict__ ids,
+                     const int64_t* __restrict__ src_off, const int64_t* __restrict__ src_row,
+                     const R* __restrict__ src_pos, const int* __restrict__ src_types, const int* __restrict__ src_seg,
+                     const R* __restrict__ src_F, const int64_t* __restrict__ dst_off,
+                     const int64_t* __restrict__ pair_base, R* __restrict__ dst_pos, int* __restrict__ dst_types,
+                     int* __restrict__ dst_seg, R* __restrict__ dst_F, int* __restrict__ dst_struct,
+                     int64_t* __restrict__ dst_row, const int* __restrict__ src_runs, const int* __restrict__ src_order,
+                     const int* __restrict__ run_base, const int64_t* __restrict__ dst_soff, int* __restrict__ dst_order,
+                     long P, const Rec<R>* __restrict__ src_pairs, const int* __restrict__ src_rev,
+                     Rec<R>* __restrict__ dst_pairs, int* __restrict__ dst_rev) {
+    const long b = blockIdx.x;
+    if (b < atom_blocks)
+        gather_atoms_block<R>(b, Na, n, T, ids, src_off, src_row, src_pos, src_types, src_seg, src_F, dst_off,
+                              pair_base, dst_pos, dst_types, dst_seg, dst_F, dst_struct, dst_row, src_runs, src_order,
+                              run_base, dst_soff, dst_order);
+    else
+        gather_pairs_block<R>(b - atom_blocks, P, n, ids, src_off, src_row, src_pairs, src_rev, dst_off, pair_base,
+                              dst_pairs, dst_rev);
+}
+
 nep_status species_sort(long Na, int T, const int* types, int* order, int64_t* soff, int* cnt, hipStream_t st);
 
 template <typename R>
@@ -902,31 +1012,29 @@ nep_status gather_impl(const Ctx& c, const nep_batch* src, const nep_neighbors* 
                        uint8_t* dst_hv, void* ws, size_t ws_bytes) {
     const int T = c.dm.T;
     hipStream_t st = c.stream;
-    const size_t need = sizeof(int64_t) * (size_t(n) + 1);
+    // with the dataset's species runs the minibatch's species order is
+    // gathered (run_base [T][n+1] after pair_base); without, it is sorted
+    const int* runs = sn->species_runs;
+    const size_t need = sizeof(int64_t) * (size_t(n) + 1) + (runs ? sizeof(int) * size_t(T) * (size_t(n) + 1) : 0);
     if (ws_bytes < need) return fail(NEP_ERR_WORKSPACE, "workspace holds %zu bytes, the gather needs %zu", ws_bytes, need);
     int64_t* pair_base = static_cast<int64_t*>(ws);
+    int* run_base = runs ? reinterpret_cast<int*>(pair_base + n + 1) : nullptr;
     const double* sE = st_ ? st_->energy : nullptr;
     const double* sW = st_ ? st_->virial : nullptr;
     const uint8_t* sH = st_ ? st_->has_virial : nullptr;
     const R* sF = st_ ? static_cast<const R*>(st_->force) : nullptr;
     NEP_LAUNCH("gather_structs", k_gather_structs, dim3(1), dim3(kScanBlock), 0, st, n, ids, src->num_structures,
                src->atom_offset, sn->row_offset, src->cells, sE, sW, sH, dst_off, pair_base, dst_cells, dst_E, dst_W,
-               dst_hv);
+               dst_hv, T, runs, run_base, dn->species_offset);
     const long P = dn->capacity;
-    if (Na > 0)
-        NEP_LAUNCH("gather_atoms", (k_gather_atoms<R>), dim3(int((Na + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
-                   st, Na, n, T, ids, src->atom_offset, sn->row_offset, static_cast<const R*>(src->positions),
-                   src->types, sn->seg_count, sF, dst_off, pair_base, static_cast<R*>(dst_pos), dst_types,
-                   dn->seg_count, static_cast<R*>(dst_F), dn->atom_struct, dn->row_offset);
-    else
-        NEP_LAUNCH("gather_atoms", (k_gather_atoms<R>), dim3(1), dim3(kNbBlock), 0, st, 0L, n, T, ids,
-                   src->atom_offset, sn->row_offset, static_cast<const R*>(src->positions), src->types, sn->seg_count,
-                   sF, dst_off, pair_base, static_cast<R*>(dst_pos), dst_types, dn->seg_count, static_cast<R*>(dst_F),
-                   dn->atom_struct, dn->row_offset);
-    if (P > 0)
-        NEP_LAUNCH("gather_pairs", (k_gather_pairs<R>), dim3(int((P + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0,
-                   st, P, n, ids, src->atom_offset, sn->row_offset, static_cast<const Rec<R>*>(sn->pairs), sn->reverse,
-                   dst_off, pair_base, static_cast<Rec<R>*>(dn->pairs), dn->reverse);
+    const long atom_blocks = Na > 0 ? (Na + kNbBlock - 1) / kNbBlock : 1, pair_blocks = (P + kNbBlock - 1) / kNbBlock;
+    NEP_LAUNCH("gather_atoms_pairs", (k_gather_atoms_pairs<R>), dim3(int(atom_blocks + pair_blocks)), dim3(kNbBlock),
+               0, st, atom_blocks, Na, n, T, ids, src->atom_offset, sn->row_offset,
+               static_cast<const R*>(src->positions), src->types, sn->seg_count, sF, dst_off, pair_base,
+               static_cast<R*>(dst_pos), dst_types, dn->seg_count, static_cast<R*>(dst_F), dn->atom_struct,
+               dn->row_offset, runs, sn->species_order, run_base, dn->species_offset, dn->species_order, P,
+               static_cast<const Rec<R>*>(sn->pairs), sn->reverse, static_cast<Rec<R>*>(dn->pairs), dn->reverse);
+    if (runs) return NEP_OK;
     return species_sort(Na, T, dst_types, dn->species_order, dn->species_offset, nullptr, st);
 }
 
@@ -1068,6 +1176,14 @@ nep_status build_neighbors_impl(const Ctx& c, const nep_batch* b, nep_neighbors*
     if (host_tot[0] > nb->capacity) {
         return fail(NEP_ERR_CAPACITY, "neighbour capacity too small: need %lld pairs, have %lld",
                     (long long)host_tot[0], (long long)nb->capacity);
+    }
+    if (nb->species_runs && Ns > 0) {
+        const long nr = 2L * Ns * T;
+        NEP_LAUNCH("species_runs", k_zero<int>, dim3(int((nr + kNbBlock - 1) / kNbBlock)), dim3(kNbBlock), 0, st, nr,
+                   nb->species_runs);
+        if (Na > 0)
+            NEP_LAUNCH("species_runs", k_species_runs, dim3(grid), dim3(kNbBlock), 0, st, Na, T, b->types,
+                       nb->atom_struct, nb->species_order, nb->species_offset, nb->species_runs);
     }
     if (Na > 0 && host_tot[0] > 0) {
         nep_status e2 = with_max_types(T, [&](auto mt) -> nep_status {

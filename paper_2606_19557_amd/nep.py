@@ -55,7 +55,8 @@ class c_neighbors(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("row_offset", C.c_void_p), ("seg_count", C.c_void_p),
                 ("pairs", C.c_void_p), ("reverse", C.c_void_p), ("atom_struct", C.c_void_p),
                 ("species_order", C.c_void_p),
-                ("species_offset", C.c_void_p), ("num_pairs", C.c_int64), ("num_angular_pairs", C.c_int64)]
+                ("species_offset", C.c_void_p), ("num_pairs", C.c_int64), ("num_angular_pairs", C.c_int64),
+                ("species_runs", C.c_void_p)]
 
 
 class c_targets(C.Structure):
@@ -231,8 +232,11 @@ class Batch:
 class Neighbors:
     """Device-resident neighbour lists (see nep_neighbors in nep.h)."""
 
-    def __init__(self, model: Model, batch: Batch, capacity: int):
+    def __init__(self, model: Model, batch: Batch, capacity: int, species_runs: bool = False):
         self._alloc(model.num_types, batch.num_atoms, capacity, model.torch_dtype, batch.positions.device)
+        if species_runs:
+            self.species_runs = torch.zeros((max(batch.num_structures, 1), model.num_types, 2), dtype=torch.int32,
+                                            device=batch.positions.device)
 
     @classmethod
     def empty(cls, num_types: int, num_atoms: int, capacity: int, dtype, device) -> "Neighbors":
@@ -249,6 +253,7 @@ class Neighbors:
         self.atom_struct = new(max(Na, 1), dtype=torch.int32, device=dev)
         self.species_order = new(max(Na, 1), dtype=torch.int32, device=dev)
         self.species_offset = new(T + 1, dtype=torch.int64, device=dev)
+        self.species_runs = None
         self.capacity = capacity
         self.num_pairs = -1
         self.num_angular_pairs = -1
@@ -257,7 +262,7 @@ class Neighbors:
         return c_neighbors(self.capacity, _ptr(self.row_offset), _ptr(self.seg_count), _ptr(self.pairs),
                            _ptr(self.reverse), _ptr(self.atom_struct), _ptr(self.species_order),
                            _ptr(self.species_offset),
-                           self.num_pairs, self.num_angular_pairs)
+                           self.num_pairs, self.num_angular_pairs, _ptr(self.species_runs))
 
     def neighbor_index(self):
         """j of every pair (host int64), decoded from the 4th slot."""
@@ -280,13 +285,16 @@ def workspace(model: Model, batch: Batch, nbr: Neighbors | None = None):
     return torch.empty(max(n, 256), dtype=torch.uint8, device=batch.positions.device)
 
 
-def nep_build_neighbors(model: Model, batch: Batch, capacity: int | None = None, ws=None) -> Neighbors:
-    """Build the lists; grows the pair buffer once when the first guess is short."""
+def nep_build_neighbors(model: Model, batch: Batch, capacity: int | None = None, ws=None,
+                        species_runs: bool = False) -> Neighbors:
+    """Build the lists; grows the pair buffer once when the first guess is short.
+    species_runs: also keep each structure's species runs (for a dataset that
+    minibatches are gathered from)."""
     if capacity is None:
         capacity = max(1024, batch.num_atoms * 64)
     ws = ws if ws is not None else workspace(model, batch)
     for _ in range(2):
-        nb = Neighbors(model, batch, capacity)
+        nb = Neighbors(model, batch, capacity, species_runs=species_runs)
         m, b, cn = model.c(), batch.c(), nb.c()
         code = lib().nep_build_neighbors(C.byref(m), C.byref(b), C.byref(cn), _ptr(ws), ws.numel(), _stream())
         nb.num_pairs, nb.num_angular_pairs = int(cn.num_pairs), int(cn.num_angular_pairs)
@@ -319,8 +327,8 @@ def nep_gather_batch(model: Model, src: Batch, src_nbr: Neighbors, src_targets, 
         F = torch.empty((num_atoms, 3), dtype=dt, device=dev)
         W = torch.empty((n, 9), dtype=torch.float64, device=dev)
         hv = torch.empty(n, dtype=torch.uint8, device=dev)
-    ws = ws if ws is not None and ws.numel() >= 8 * (n + 1) else torch.empty(8 * (n + 1), dtype=torch.uint8,
-                                                                             device=dev)
+    need = 8 * (n + 1) + (4 * T * (n + 1) if src_nbr.species_runs is not None else 0)
+    ws = ws if ws is not None and ws.numel() >= need else torch.empty(need, dtype=torch.uint8, device=dev)
     m, sb, sn, cn = model.c(), src.c(), src_nbr.c(), nb.c()
     stg = src_targets.c() if src_targets is not None else None
     _check(lib().nep_gather_batch(C.byref(m), C.byref(sb), C.byref(sn), C.byref(stg) if stg is not None else None,

@@ -27,7 +27,7 @@ class Dataset:
     def __init__(self, model: Model, host_batch, energy, force, virial, has_virial=None, device="cuda",
                  capacity: int | None = None, zbl: Zbl | None = None):
         batch = Batch.from_host(host_batch, dtype=model.torch_dtype, device=device)
-        nbr = nep_build_neighbors(model, batch, capacity)
+        nbr = nep_build_neighbors(model, batch, capacity, species_runs=True)
         targets = Targets(energy, force, virial, has_virial, dtype=model.torch_dtype, device=device)
         if zbl is not None:
             # the ZBL term has no parameter: training NEP on targets minus ZBL is

@@ -23,20 +23,48 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _dataset(name, idx, dtype="f32"):
+def _dataset(name, idx, dtype="f32", runs=True):
     md, m, b, th, s, tg = fixture(name, idx)
     b, th, s, tg = device_inputs(dtype, b, th, s, tg)
     model = N.Model.from_dict(md, dtype=dtype)
-    data = train.Dataset(model, b, *tg)
+    if runs:
+        data = train.Dataset(model, b, *tg)
+    else:
+        # lists without species runs: the gather sorts each minibatch by species
+        gb = N.Batch.from_host(b, dtype=model.torch_dtype)
+        nb = N.nep_build_neighbors(model, gb)
+        data = train.Dataset.from_device(model, gb, nb, N.Targets(*tg, dtype=model.torch_dtype), b.atom_offset)
     td = model.torch_dtype
     return md, model, data, torch.tensor(th, dtype=td, device="cuda"), torch.tensor(s, dtype=td, device="cuda"), b, tg
 
 
-@pytest.mark.parametrize("name,dtype", [("fcc_uneven_256", "f32"), ("alloy4_1024", "f64")])
-def test_gather_equals_direct_build(name, dtype):
-    _say(f"gather {name} {dtype}")
+def test_species_runs_match_species_order():
+    """Each structure's run {start, end} in species_order, recomputed on the host."""
+    _say("species runs alloy4_1024")
+    md, model, data, theta, qs, b, tg = _dataset("alloy4_1024", list(range(12)))
+    nb = data.nbr
+    assert nb.species_runs is not None
+    runs = nb.species_runs.cpu().numpy()
+    order = nb.species_order.cpu().numpy()[: b.num_atoms]
+    soff = nb.species_offset.cpu().numpy()
+    struct = nb.atom_struct.cpu().numpy()
+    T = model.num_types
+    want = np.zeros((b.num_structures, T, 2), dtype=np.int64)
+    for t in range(T):
+        for p in range(soff[t], soff[t + 1]):
+            s = struct[order[p]]
+            if want[s, t, 1] == 0:
+                want[s, t, 0] = p
+            want[s, t, 1] = p + 1
+    assert np.array_equal(runs, want)
+
+
+@pytest.mark.parametrize("name,dtype,runs", [("fcc_uneven_256", "f32", True), ("alloy4_1024", "f64", True),
+                                             ("alloy4_1024", "f32", False)])
+def test_gather_equals_direct_build(name, dtype, runs):
+    _say(f"gather {name} {dtype} runs={runs}")
     idx = list(range(10))
-    md, model, data, theta, qs, b, tg = _dataset(name, idx, dtype)
+    md, model, data, theta, qs, b, tg = _dataset(name, idx, dtype, runs)
     pick = [7, 2, 9, 0, 4]
     gb, gnb, gtg = data.minibatch(pick, lambdas=(1.0, 1.0, 0.1))
     sub = b.subset(pick)
