@@ -1933,7 +1933,7 @@ k_network_backward_lane(const Dims dm, const R* __restrict__ theta, const R* __r
                         R* __restrict__ abar_out, R* __restrict__ alpha_out, R* __restrict__ beta_out,
                         R* __restrict__ gamma_out) {
     constexpr int D = Sh::D, MC = LaneNet<R>::MC, LD = MC + 1;
-    __shared__ R tb[4][64 * LD];
+    __shared__ R tb[3][64 * LD];
     const int T = dm.T, H = dm.H;
     int a;
     long lo = 0, hi = 0;
@@ -1952,26 +1952,30 @@ k_network_backward_lane(const Dims dm, const R* __restrict__ theta, const R* __r
         dk[v] = qscale[v] * dq_in[ia * D + v];
         z[v] = R(0);
     }
+    const R* __restrict__ trow = t_in + (lo + (live ? l : 0)) * H;
     for (int mu0 = 0; mu0 < H; mu0 += MC) {
         const int mn = H - mu0 < MC ? H - mu0 : MC;
-        for (int x = l; x < nat * mn; x += 64) {
-            const int sl = x / mn, m = x % mn;
-            tb[3][sl * LD + m] = t_in[(lo + sl) * H + mu0 + m];
-        }
-        __syncthreads();
-        for (int m = 0; m < mn; ++m) {
-            const R* __restrict__ w = W0 + (long)(mu0 + m) * D;
-            R da = R(0);
+        // the lane's own activations of the tile's units, all loads in flight
+        // at once (units past the layer's end read unit mu0 and are unused)
+        R tv[MC];
 #pragma unroll
-            for (int v = 0; v < D; ++v) da += w[v] * dk[v];
-            const R t = live ? tb[3][l * LD + m] : R(0);
-            const R sp = R(1) - t * t, wm = w1[mu0 + m];
-            tb[0][l * LD + m] = wm * sp * (eb - R(2) * t * da);
-            tb[1][l * LD + m] = wm * sp;
-            tb[2][l * LD + m] = eb * t + sp * da;
-            const R c2 = R(-2) * wm * t * sp * da;
+        for (int m = 0; m < MC; ++m) tv[m] = trow[mu0 + (m < mn ? m : 0)];
 #pragma unroll
-            for (int v = 0; v < D; ++v) z[v] += w[v] * c2;
+        for (int m = 0; m < MC; ++m) {
+            if (m < mn) {
+                const R* __restrict__ w = W0 + (long)(mu0 + m) * D;
+                R da = R(0);
+#pragma unroll
+                for (int v = 0; v < D; ++v) da += w[v] * dk[v];
+                const R t = live ? tv[m] : R(0);
+                const R sp = R(1) - t * t, wm = w1[mu0 + m];
+                tb[0][l * LD + m] = wm * sp * (eb - R(2) * t * da);
+                tb[1][l * LD + m] = wm * sp;
+                tb[2][l * LD + m] = eb * t + sp * da;
+                const R c2 = R(-2) * wm * t * sp * da;
+#pragma unroll
+                for (int v = 0; v < D; ++v) z[v] += w[v] * c2;
+            }
         }
         __syncthreads();
         for (int x = l; x < nat * mn; x += 64) {
