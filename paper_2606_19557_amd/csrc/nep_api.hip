@@ -107,6 +107,26 @@ int resident_blocks(const void* fn, int threads, size_t shm) {
     return n;
 }
 
+// The row-owned coefficient sweep's slot geometry for host callers: its
+// bank-conflict search costs about 0.1 ms, so it runs once per shape.
+CgRowsGeom cg_rows_geom_host(int T, int NA, int KA, int LM, int rbytes, int rows) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int>, CgRowsGeom> cache;
+    const auto key = std::make_tuple(NA, KA, LM, rbytes, rows);
+    CgRowsGeom g{};
+    {
+        std::lock_guard<std::mutex> l(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) g = it->second;
+    }
+    if (g.S == 0) {
+        g = cg_rows_slots(NA, KA, LM, rbytes, rows);
+        std::lock_guard<std::mutex> l(mu);
+        cache[key] = g;
+    }
+    return cg_rows_place(g, T, NA, KA, rbytes);
+}
+
 // ------------------------------------------------------------------ shapes
 
 #define NEP_SHAPE(KR, KA, NR, NA, L, H4, H5)                              \
@@ -215,7 +235,7 @@ Layout make_layout(const Dims& dm, const Plan& plan, bool f64, int Ns, long Na, 
     if (plan.cg_rows > 0) {
         // row-owned sweep: one partial row per wavefront, at most cg_blocks
         // wavefronts and no more than its species tiles, in whole blocks
-        const CgRowsGeom g = cg_rows_geom(dm.T, dm.NA, dm.KA, dm.LM, int(r), plan.cg_rows);
+        const CgRowsGeom g = cg_rows_geom_host(dm.T, dm.NA, dm.KA, dm.LM, int(r), plan.cg_rows);
         const long nw = cg_rows_waves(g.wave_bytes);
         const long tiles = (Na + g.teams - 1) / g.teams + dm.T;
         long waves = tiles < plan.cg_blocks ? tiles : plan.cg_blocks;

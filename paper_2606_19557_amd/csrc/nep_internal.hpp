@@ -160,6 +160,8 @@ T with_cg_team_size(int s, F&& f) {
 // device holds at once for kernel `fn` (occupancy per CU times CUs, cached per
 // kernel, device and launch shape); -1 if the runtime query fails.
 int resident_blocks(const void* fn, int threads, size_t shm);
+// cg_rows_geom with the T-independent part computed once per shape (host).
+CgRowsGeom cg_rows_geom_host(int T, int NA, int KA, int LM, int rbytes, int rows);
 
 // Per-shape pipeline (forward / loss+grad / backward / descriptors).
 using ShapeFn = nep_status (*)(const Ctx&);

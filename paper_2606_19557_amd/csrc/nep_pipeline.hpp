@@ -40,7 +40,7 @@ nep_status run_shape(const Ctx& c) {
     const size_t cg_shm = cg_bytes(team_cg);
     // the row-owned form: LDS of one wavefront, wavefronts per block
     const CgRowsGeom cg_rows_gm =
-        cg_rows_geom(dm.T, Sh::NA, Sh::KA, Sh::LM, int(sizeof(R)), c.plan.cg_rows > 0 ? c.plan.cg_rows : 1);
+        cg_rows_geom_host(dm.T, Sh::NA, Sh::KA, Sh::LM, int(sizeof(R)), c.plan.cg_rows > 0 ? c.plan.cg_rows : 1);
     const int cg_rows_nw = cg_rows_waves(cg_rows_gm.wave_bytes);
     if (c.mode == Mode::LossGrad || c.mode == Mode::Backward) {
         if (c.plan.cg_rows > 0 && cg_rows_gm.wave_bytes > 160 * 1024)
