@@ -46,16 +46,40 @@ k_structure(int Ns, long Na, const int64_t* __restrict__ off, const R* __restric
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[c] = 0.0;
     const double cf = 2.0 * lam_f / (3.0 * double(Na));
-    for (long i = a0 + threadIdx.x; i < a1; i += kRedBlock) {
-        acc[0] += double(E_at[i]);
+    // UN atoms per thread per round, every load of the round issued before
+    // the first sum (an atom past the structure's end reads its last atom and
+    // adds nothing), so a large structure is not one load latency per atom
+    constexpr int UN = 4;
+    for (long i0 = a0 + threadIdx.x; i0 < a1; i0 += UN * kRedBlock) {
+        R e[UN], wv[UN][9], f[UN][3], ft[UN][3];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) acc[1 + c] += double(W_at[i * 9 + c]);
-        if (loss) {
+        for (int u = 0; u < UN; ++u) {
+            const long i = min(i0 + long(u) * kRedBlock, a1 - 1);
+            e[u] = E_at[i];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double r = double(F[i * 3 + d]) - double(Ft[i * 3 + d]);
-                acc[10] += r * r;
-                ubar[i * 3 + d] = R(cf * r);
+            for (int c = 0; c < 9; ++c) wv[u][c] = W_at[i * 9 + c];
+            if (loss) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    f[u][d] = F[i * 3 + d];
+                    ft[u][d] = Ft[i * 3 + d];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const long i = i0 + long(u) * kRedBlock;
+            if (i >= a1) continue;
+            acc[0] += double(e[u]);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc[1 + c] += double(wv[u][c]);
+            if (loss) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double r = double(f[u][d]) - double(ft[u][d]);
+                    acc[10] += r * r;
+                    ubar[i * 3 + d] = R(cf * r);
+                }
             }
         }
     }
