@@ -59,6 +59,29 @@ def test_species_runs_match_species_order():
     assert np.array_equal(runs, want)
 
 
+def test_gather_more_ids_than_one_scan_chunk():
+    """1,100 ids (more than the gather's 1,024-structure scan chunk, with
+    repeats): the species order gathered from the dataset's runs equals a
+    stable sort of the gathered species, the species offsets their counts, and
+    everything equals the minibatch gathered without the runs (sorted)."""
+    _say("gather 1100 ids alloy4_1024")
+    md, model, data, theta, qs, b, tg = _dataset("alloy4_1024", list(range(10)))
+    _, _, data2, _, _, _, _ = _dataset("alloy4_1024", list(range(10)), runs=False)
+    pick = np.random.default_rng(7).integers(0, 10, size=1100).tolist()
+    gb, gnb, gtg = data.minibatch(pick)
+    gb2, gnb2, gtg2 = data2.minibatch(pick)
+    types = gb.types.cpu().numpy()
+    T = model.num_types
+    assert np.array_equal(gnb.species_order.cpu().numpy()[: gb.num_atoms], np.argsort(types, kind="stable"))
+    want_off = np.concatenate([[0], np.cumsum(np.bincount(types, minlength=T))])
+    assert np.array_equal(gnb.species_offset.cpu().numpy(), want_off)
+    assert torch.equal(gb.atom_offset, gb2.atom_offset) and torch.equal(gb.positions, gb2.positions)
+    for k in ("row_offset", "seg_count", "atom_struct", "species_order", "species_offset"):
+        assert torch.equal(getattr(gnb, k), getattr(gnb2, k)), k
+    P = gnb.num_pairs
+    assert torch.equal(gnb.pairs[:P], gnb2.pairs[:P]) and torch.equal(gnb.reverse[:P], gnb2.reverse[:P])
+
+
 @pytest.mark.parametrize("name,dtype,runs", [("fcc_uneven_256", "f32", True), ("alloy4_1024", "f64", True),
                                              ("alloy4_1024", "f32", False)])
 def test_gather_equals_direct_build(name, dtype, runs):
