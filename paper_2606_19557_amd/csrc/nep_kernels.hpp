@@ -272,9 +272,12 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
     const int i = live ? order[lo + team] : 0;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
     int64_t p = live ? row[i] : 0;
-    R qR[NR];
+    // without the network in the sweep a lane needs only the radial rows it
+    // stores, n = lane + S o: NR_OWN of them
+    constexpr int NR_OWN = FUSE == 0 ? (NR + S - 1) / S : NR;
+    R qR[NR_OWN];
 #pragma unroll
-    for (int n = 0; n < NR; ++n) qR[n] = R(0);
+    for (int n = 0; n < NR_OWN; ++n) qR[n] = R(0);
     R acc[NA][OWN];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
@@ -326,10 +329,22 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) Sb[kk] = team_sum<S>(Sb[kk]);
         const R* __restrict__ cR = theta + (long)((a * T + b) * NR) * KR;
+        if constexpr (FUSE == 0) {
+            // the lane's own coefficient rows (vector loads; a row past N_R
+            // reads the last one and is never stored)
 #pragma unroll
-        for (int n = 0; n < NR; ++n)
+            for (int o = 0; o < NR_OWN; ++o) {
+                const int n = lane + S * o;
+                const R* __restrict__ cr = cR + (n < NR ? n : NR - 1) * KR;
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) qR[n] += cR[n * KR + kk] * Sb[kk];
+                for (int kk = 0; kk < KR; ++kk) qR[o] += cr[kk] * Sb[kk];
+            }
+        } else {
+#pragma unroll
+            for (int n = 0; n < NR; ++n)
+#pragma unroll
+                for (int kk = 0; kk < KR; ++kk) qR[n] += cR[n * KR + kk] * Sb[kk];
+        }
         if (live) {
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk)
@@ -366,7 +381,11 @@ k_descriptor(const Dims dm, const R* __restrict__ theta, const int* __restrict__
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         if (d < NR) {
-            qv[d] = qR[d];
+            // (FUSE 0: right only in the lane that stores entry d, d % S == lane)
+            if constexpr (FUSE == 0)
+                qv[d] = qR[d / S];
+            else
+                qv[d] = qR[d];
         } else if (d < NR + L * NA) {
             qv[d] = qA[d - NR];
         } else if (Sh::H4 && d < NR + (L + 1) * NA) {
@@ -713,9 +732,12 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ or
     for (int d = 0; d < 3; ++d) ui[d] = live ? ubar[(long)i * 3 + d] : R(0);
 #pragma unroll
     for (int c = 0; c < 9; ++c) U[c] = live ? R(Ubar[(long)s * 9 + c]) : R(0);
-    R dqR[NR];
+    // without the network in the sweep a lane needs only the radial rows it
+    // stores, n = lane + S o
+    constexpr int NR_OWN = NET ? NR : (NR + S - 1) / S;
+    R dqR[NR_OWN];
 #pragma unroll
-    for (int n = 0; n < NR; ++n) dqR[n] = R(0);
+    for (int n = 0; n < NR_OWN; ++n) dqR[n] = R(0);
     R acc[NA][OWN];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
@@ -799,10 +821,20 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ or
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) Sb[kk] = team_sum<S>(Sb[kk]);
         const R* __restrict__ cR = theta + (long)((a * T + b) * NR) * KR;
+        if constexpr (!NET) {
 #pragma unroll
-        for (int n = 0; n < NR; ++n)
+            for (int o = 0; o < NR_OWN; ++o) {
+                const int n = lane + S * o;
+                const R* __restrict__ cr = cR + (n < NR ? n : NR - 1) * KR;
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) dqR[n] += cR[n * KR + kk] * Sb[kk];
+                for (int kk = 0; kk < KR; ++kk) dqR[o] += cr[kk] * Sb[kk];
+            }
+        } else {
+#pragma unroll
+            for (int n = 0; n < NR; ++n)
+#pragma unroll
+                for (int kk = 0; kk < KR; ++kk) dqR[n] += cR[n * KR + kk] * Sb[kk];
+        }
         if (live) {
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk)
@@ -864,7 +896,10 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ or
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         if (d % S != lane) continue;
-        dq_out[(long)i * D + d] = d < NR ? dqR[d] : part[d - NR];
+        if constexpr (!NET)
+            dq_out[(long)i * D + d] = d < NR ? dqR[d / S] : part[d - NR];
+        else
+            dq_out[(long)i * D + d] = d < NR ? dqR[d] : part[d - NR];
     }
 #pragma unroll
     for (int n = 0; n < NA; ++n)
@@ -873,7 +908,7 @@ k_tangent(const Dims dm, const R* __restrict__ theta, const int* __restrict__ or
             const int lm = lane + S * o;
             if (lm < LM) dA_out[((long)i * NA + n) * LM + lm] = acc[n][o];
         }
-    if (NET) {
+    if constexpr (NET) {
         R dq[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) dq[d] = d < NR ? dqR[d] : part[d - NR];
