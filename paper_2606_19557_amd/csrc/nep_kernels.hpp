@@ -528,18 +528,30 @@ __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __
     for (int b = 0; b < T; ++b) {
         const int tot = live ? seg[(i * T + b) * 2] : 0;
         const int ang = live ? seg[(i * T + b) * 2 + 1] : 0;
-        // radial force coefficients eps_k = sum_n e_n c_R[a][b][n][k]
+        // radial force coefficients eps_k = sum_n e_n c_R[a][b][n][k]: each
+        // lane of the team sums its columns k = lane + S o (a column past K_R
+        // reads the last one and is dropped), then the team gathers them
         R epsk[KR];
         const R* __restrict__ cRab = theta + (long)((a * T + b) * NR) * KR;
+        {
+            constexpr int KO = (KR + S - 1) / S;
+            R mine[KO];
 #pragma unroll
-        for (int kk = 0; kk < KR; ++kk) epsk[kk] = R(0);
-        if (live) {
+            for (int o = 0; o < KO; ++o) mine[o] = R(0);
+            if (live) {
 #pragma unroll
-            for (int n = 0; n < NR; ++n) {
-                const R en = ei[n];
+                for (int n = 0; n < NR; ++n) {
+                    const R en = ei[n];
 #pragma unroll
-                for (int kk = 0; kk < KR; ++kk) epsk[kk] += en * cRab[n * KR + kk];
+                    for (int o = 0; o < KO; ++o) {
+                        const int kk = lane + S * o;
+                        mine[o] += en * cRab[n * KR + (kk < KR ? kk : KR - 1)];
+                    }
+                }
             }
+            const int base = int(threadIdx.x) & ~(S - 1);
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) epsk[kk] = __shfl(mine[kk / S], base + kk % S, 64);
         }
         const R* __restrict__ cA = theta + dm.offA + (long)((a * T + b) * NA) * KA;
         // the next record and reverse index are loaded one iteration ahead,
