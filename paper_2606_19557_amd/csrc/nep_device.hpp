@@ -465,8 +465,8 @@ __host__ __device__ constexpr int cg_slot_conflicts(int S, int slot_w, int ts_w,
 }
 // LDS layout of the row-owned angular coefficient sweep (one region per
 // wavefront): G [T][N_A][K_A]; a slot per lane holding one pair's Y [24],
-// (v.grad) Y [24] and the interleaved (f_k, (v.r^) f'_k) pairs, padded to
-// whole 16-byte vectors; the team stride padded by whole vectors to the
+// (v.grad) Y [24], the interleaved (f_k, (v.r^) f'_k) pairs and the pair's
+// neighbour-species segment, padded to whole 16-byte vectors; the team stride padded by whole vectors to the
 // fewest bank conflicts for 8-lane groups on 32 banks and 16-lane groups on
 // 64 banks; then the teams' segment tables. cg_rows_slots fixes the slots
 // (no dependence on T: kernels take it as a compile-time constant, the
@@ -476,7 +476,7 @@ __host__ __device__ constexpr CgRowsGeom cg_rows_slots(int NA, int KA, int LM, i
     g.S = (NA + rows - 1) / rows;
     g.teams = 64 / g.S;
     g.vec = 16 / rbytes;
-    g.kfp = (2 * KA + g.vec - 1) / g.vec * g.vec;
+    g.kfp = (2 * KA + 1 + g.vec - 1) / g.vec * g.vec;  // f, f' pairs and the pair's segment
     g.slot = 2 * LM + g.kfp;
     const int sw = g.slot * rbytes / 4;
     int best = -1, best_pad = 0;

@@ -1151,44 +1151,31 @@ __device__ __forceinline__ void row_adjoints(int n, const R* __restrict__ A, con
     }
 }
 
-// Cursor over one atom's angular pairs in batches of up to S that stay inside
-// one neighbour-species segment: segment b, first pair kin of the batch inside
-// it, the segment's angular count and its first row offset. tab holds the
-// team's segment table: angular starts [T+1], then row offsets [T].
-struct SegCursor {
-    int b, kin, ang, pos;
-    __device__ __forceinline__ void next_segment(const int* tab, int T) {
-        kin = 0;
-        ang = 0;
-        do {
-            ++b;
-            if (b < T) ang = tab[b + 1] - tab[b];
-        } while (b < T && ang == 0);
-        pos = b < T ? tab[T + 1 + b] : 0;
-    }
-    __device__ __forceinline__ void first(const int* tab, int T) {
-        b = -1;
-        next_segment(tab, T);
-    }
-    template <int S>
-    __device__ __forceinline__ void advance(const int* tab, int T) {
-        if (b >= T) return;
-        kin += S;
-        if (kin >= ang) next_segment(tab, T);
-    }
-};
+// A small integer carried bit for bit in a slot's spare value.
+template <typename R>
+__device__ __forceinline__ R slot_tag(int b);
+template <>
+__device__ __forceinline__ float slot_tag<float>(int b) { return __int_as_float(b); }
+template <>
+__device__ __forceinline__ double slot_tag<double>(int b) { return __longlong_as_double((long long)b); }
+template <typename R>
+__device__ __forceinline__ int slot_untag(R v);
+template <>
+__device__ __forceinline__ int slot_untag<float>(float v) { return __float_as_int(v); }
+template <>
+__device__ __forceinline__ int slot_untag<double>(double v) { return (int)__double_as_longlong(v); }
 
 // dL/dc_A[a][b][n][k] (the sum of k_angular_coeff_grad), rows per lane: a team
 // of S = ceil(N_A / ROWS) lanes per atom, lane l holding rows
 // n = l ROWS .. l ROWS + ROWS - 1 of the atom's Bp and Q in registers. Each
 // batch, the team's lanes evaluate one pair each (basis, harmonics and their
-// derivative along v) and publish (Y, v.dY, f, (v.r^) f') in their LDS slots;
-// every lane then runs the whole batch for its own rows, forming P_n and R_n
-// in full, so the outer product over k needs neither an exchange nor a team
-// sum. Batches stay inside one neighbour-species segment and each team walks
-// its atom's segments on its own; a lane adds its sums into the wavefront's
+// derivative along v) and publish (Y, v.dY, f, (v.r^) f', segment) in their
+// LDS slots; every lane then runs the whole batch for its own rows, forming
+// P_n and R_n in full, so the outer product over k needs neither an exchange
+// nor a team sum. A batch takes the atom's next S angular pairs whatever
+// their neighbour species; a lane adds its sums into the wavefront's
 // accumulator G[a][b] (LDS atomics, in the wavefront's fixed instruction
-// order: bitwise repeatable) when its team moves to another segment. Pair
+// order: bitwise repeatable) when the pairs move to another segment b. Pair
 // records are loaded two batches ahead and the neighbours' seeds one batch
 // ahead. Each wavefront owns one G and walks its own tiles; the block's
 // wavefronts add their G in wavefront order into the block's partial row.
@@ -1295,21 +1282,26 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
             }
         }
         X::wave_fence();
-        // batches t, t+1, t+2 and the records of t and t+1
-        SegCursor cA{T, 0, 0, 0};
-        if (live) cA.first(tab, T);
-        SegCursor cB = cA;
-        cB.advance<S>(tab, T);
-        SegCursor cC = cB;
-        cC.advance<S>(tab, T);
-        auto fetch = [&](const SegCursor& c) {
-            Rec<R> rec{};
-            if (c.b < T && c.kin + lane < c.ang) rec = pairs[p0 + c.pos + c.kin + lane];
-            return rec;
+        // The atom's angular pairs in batches of S taken across its neighbour-
+        // species segments (kappa = 0 .. A-1 numbers them segment after
+        // segment): a batch pads only at the atom's end, not at every
+        // segment's. locate(kappa) gives the pair's row index and segment b
+        // from the team's table (cum[b] = first kappa of segment b).
+        const int A = live ? tab[T] : 0;
+        auto locate = [&](int kap, int* bo) -> int64_t {
+            int bb = 0;
+            for (int t = 1; t < T; ++t) bb = tab[t] <= kap ? t : bb;
+            *bo = bb;
+            return p0 + tab[T + 1 + bb] + (kap - tab[bb]);
         };
-        Rec<R> recA = fetch(cA), recB = fetch(cB);
+        // records of batches t and t+1 and the neighbours' seeds of t; a lane
+        // past the atom's last pair reads that pair again and drops it
+        int bA = 0, bB = 0;
+        Rec<R> recA{}, recB{};
         R ujA[3] = {R(0), R(0), R(0)};
-        if (cA.b < T && cA.kin + lane < cA.ang) {
+        if (A > 0) {
+            recA = pairs[locate(lane < A ? lane : A - 1, &bA)];
+            recB = pairs[locate(S + lane < A ? S + lane : A - 1, &bB)];
             const long j = rec_j(recA);
 #pragma unroll
             for (int d = 0; d < 3; ++d) ujA[d] = ubar[j * 3 + d];
@@ -1334,24 +1326,23 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                 }
             }
         };
-        while (cA.b < T) {
+        for (int base = 0; base < A; base += S) {
             // loads for the next batches: the records of t+2, then the
             // neighbours' seeds of t+1 (issued last, so that waiting for them
-            // at the next batch does not also wait for the records). Both are
-            // issued by every lane of the loop, a lane past its segment's end
-            // reading the atom's first pair and atom 0 (both exist for an atom
-            // with angular pairs) and never using what it read: with no
-            // branch around them the compiler waits for exactly the loads a
-            // value needs instead of all of them.
-            const Rec<R> recC = pairs[cC.b < T && cC.kin + lane < cC.ang ? p0 + cC.pos + cC.kin + lane : p0];
+            // at the next batch does not also wait for the records), by every
+            // lane with no branch around them: the compiler then waits for
+            // exactly the loads a value needs instead of all of them
+            int bC;
+            const int kC = base + 2 * S + lane;
+            const Rec<R> recC = pairs[locate(kC < A ? kC : A - 1, &bC)];
             R ujB[3];
             {
-                const long j = cB.b < T && cB.kin + lane < cB.ang ? long(rec_j(recB)) : 0L;
+                const long j = rec_j(recB);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ujB[d] = ubar[j * 3 + d];
             }
-            // phase 1: this lane's pair of batch t into its slot
-            const int nq = cA.ang - cA.kin < S ? cA.ang - cA.kin : S;
+            // phase 1: this lane's pair of batch t into its slot, with its segment
+            const int nq = A - base < S ? A - base : S;
             if (lane < nq) {
                 const R rv[3] = {recA.x, recA.y, recA.z};
                 const R r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
@@ -1375,7 +1366,7 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) {
                             const int x = c * VEC + e, k = x / 2;
-                            w[e] = k < KA ? ((x & 1) ? fap[k] * vu : fa[k]) : R(0);
+                            w[e] = k < KA ? ((x & 1) ? fap[k] * vu : fa[k]) : x == 2 * KA ? slot_tag<R>(bA) : R(0);
                         }
                         sl[2 * LM / VEC + c] = w;
                     }
@@ -1397,11 +1388,8 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                 }
             }
             X::wave_fence();
-            // phase 2: the batch's pairs for this lane's rows
-            if (cA.b != cur_b) {
-                flush();
-                cur_b = cA.b;
-            }
+            // phase 2: the batch's pairs for this lane's rows; the sums go to
+            // G[a][b] whenever the pairs move to another segment b
 #pragma unroll 1
             for (int q = 0; q < nq; ++q) {
                 const V* sl = reinterpret_cast<const V*>(myslots + q * SLOT);
@@ -1421,6 +1409,11 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                             rn[r] += Q[r][c * VEC + e] * y[e];
                         }
                 }
+                const int bq = slot_untag<R>(myslots[q * SLOT + 2 * LM + 2 * KA]);
+                if (bq != cur_b) {
+                    flush();
+                    cur_b = bq;
+                }
 #pragma unroll
                 for (int c = 0; c < KFP / VEC; ++c) {
                     const V w = sl[2 * LM / VEC + c];  // (f_k, (v.r^) f'_k) pairs
@@ -1437,11 +1430,10 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                 }
             }
             X::wave_fence();
-            cA = cB;
-            cB = cC;
-            cC.advance<S>(tab, T);
             recA = recB;
             recB = recC;
+            bA = bB;
+            bB = bC;
 #pragma unroll
             for (int d = 0; d < 3; ++d) ujA[d] = ujB[d];
         }
