@@ -13,6 +13,9 @@ namespace nep {
 
 // Threads per block of the atom and pair-sweep kernels.
 constexpr int kBlock = 256;
+// s_waitcnt immediate that waits for vmcnt 0 only (gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
 
 // Runtime model dimensions (host computes, kernels take by value).
 struct Dims {
@@ -506,6 +509,28 @@ __host__ __device__ constexpr CgRowsGeom cg_rows_geom(int T, int NA, int KA, int
 __host__ __device__ constexpr int cg_rows_waves(size_t wave_bytes) {
     const size_t cu = 160 * 1024, per_cu = cu / wave_bytes;
     return (cu / (4 * wave_bytes)) * 4 == per_cu ? 4 : (cu / (2 * wave_bytes)) * 2 == per_cu ? 2 : 1;
+}
+
+// LDS of the force sweep beyond its static blocks of B, for a model of T
+// species with N_A angular channels, K_A angular and K_R radial basis
+// functions, TEAMS atoms per block and reals of rbytes bytes: c^A[a][b] of
+// the block's species a for every neighbour species b (rows of N_A K_A reals
+// padded by one 16-byte vector, so that teams at different b read different
+// banks), each team's radial force coefficients eps_k[b][K_R] (whole 16-byte
+// vectors per team), and each team's segment table (T + 1 int4 entries).
+struct ForceLds {
+    int cas, eps_team;
+    size_t off_eps, off_tab, bytes;
+};
+__host__ __device__ constexpr ForceLds force_lds(int T, int NA, int KA, int KR, int teams, int rbytes) {
+    ForceLds g{};
+    const int vec = 16 / rbytes;
+    g.cas = (NA * KA + vec - 1) / vec * vec + vec;
+    g.eps_team = (T * KR + vec - 1) / vec * vec;
+    g.off_eps = size_t(T) * g.cas * rbytes;
+    g.off_tab = g.off_eps + size_t(teams) * g.eps_team * rbytes;
+    g.bytes = g.off_tab + size_t(teams) * (T + 1) * 16;
+    return g;
 }
 
 }  // namespace nep

@@ -504,20 +504,115 @@ __device__ __forceinline__ void moment_adjoints(int lane, const R* __restrict__ 
 
 // ------------------------------------------------------------------- force
 
-// The force pass of one atom's team: for every pair of atom i's row,
-// h_ij = dE_i/dr_ij from the atom's own B = dE_i/dA (Bk, the team's LDS copy)
-// and e = dE_i/dq (ei), the radial part through eps_k = sum_n e_n c_R[a][b][n][k]
-// (one direction per pair); the atom's own-direction sum sum_j h_ij, its
-// virial -sum_j r_ij (x) h_ij, and -h_ij written into the slot of the reverse
-// pair (j, i), so that k_force_gather completes F_j = sum h_jk + sum (-h_kj)
-// with contiguous reads and no atomics.
+// One pair of atom i's row in the force pass: h_ij = dE_i/dr_ij from the
+// radial force coefficients eps_k = sum_n e_n c_R[a][b][n][k] (epsk) and, for
+// an angular pair, from c^A[a][b] (cA) and the atom's own B = dE_i/dA (Bk);
+// -h_ij goes to the slot q of the reverse pair (j, i) (zero to the pair's own
+// slot pos when it has none), h_ij to the atom's own-direction sum F and
+// -r_ij (x) h_ij to its virial Wv.
+template <typename R, class Sh>
+__device__ __forceinline__ void force_pair(const Rec<R>& pr, int q, int64_t pos, bool angular, const R* epsk,
+                                           const R* cA, const R* Bk, R rcR, R irR, R rcA, R irA,
+                                           Rec<R>* __restrict__ h_in, R* F, R* Wv) {
+    constexpr int NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM;
+    const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
+    const R ir = R(1) / r;
+    const R u[3] = {pr.x * ir, pr.y * ir, pr.z * ir};
+    R f[KR], fp[KR];
+    cheb_basis<R, KR, true>(r, rcR, irR, f, fp);
+    R sr = R(0);
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) sr += epsk[kk] * fp[kk];
+    R hv[3] = {sr * u[0], sr * u[1], sr * u[2]};
+    if (angular) {
+        R fa[KA], fap[KA];
+        cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
+        R c[LM], cp[LM];
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) c[lm] = cp[lm] = R(0);
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            R g = R(0), gp = R(0);
+#pragma unroll
+            for (int kk = 0; kk < KA; ++kk) {
+                g += cA[n * KA + kk] * fa[kk];
+                gp += cA[n * KA + kk] * fap[kk];
+            }
+#pragma unroll
+            for (int lm = 0; lm < LM; ++lm) {
+                c[lm] += Bk[n * LM + lm] * g;
+                cp[lm] += Bk[n * LM + lm] * gp;
+            }
+        }
+        // G = grad_u sum_lm c_lm Y_lm(u); Y_lm is homogeneous of degree l, so
+        // u . G = sum_lm l c_lm Y_lm (Euler) and the tangential part of
+        // the gradient is G - (u . G) u.
+        R Y[LM], G[3];
+        solid_harmonics<R, R, Sh::L>(u[0], u[1], u[2], Y);
+        R sY = R(0);
+#pragma unroll
+        for (int lm = 0; lm < LM; ++lm) sY += cp[lm] * Y[lm];
+        solid_harmonics_grad<R, Sh::L>(u[0], u[1], u[2], c, G);
+        const R lY = u[0] * G[0] + u[1] * G[1] + u[2] * G[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) hv[d] += sY * u[d] + (G[d] - lY * u[d]) * ir;
+    }
+    if (q >= 0) {
+        Rec<R> ho;
+        ho.x = -hv[0];
+        ho.y = -hv[1];
+        ho.z = -hv[2];
+        ho.w = R(0);
+        h_in[q] = ho;  // -dE_i/dr_ij is the pair's contribution to F_j
+    } else {
+        // no reverse pair (|r| at the cutoff in one direction only):
+        // nothing else writes this pair's own slot
+        h_in[pos] = Rec<R>{};
+    }
+    const R rv[3] = {pr.x, pr.y, pr.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] += hv[d];
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) Wv[al * 3 + be] -= rv[al] * hv[be];
+}
+
+// The team sums of an atom's own-direction force and virial, stored by the
+// lanes that own each component.
+template <typename R, int S>
+__device__ __forceinline__ void force_store(int lane, bool live, int i, R* F, R* Wv, R* __restrict__ Fown_out,
+                                            R* __restrict__ Wat_out) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] = team_sum<S>(F[d]);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Wv[c] = team_sum<S>(Wv[c]);
+    if (live) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (d % S == lane) Fown_out[(long)i * 3 + d] = F[d];
+#pragma unroll
+        for (int c = 0; c < 9; ++c)
+            if (c % S == lane) Wat_out[(long)i * 9 + c] = Wv[c];
+    }
+}
+
+// The force pass of one atom's team inside the descriptor sweep: for every
+// pair of atom i's row, h_ij = dE_i/dr_ij from the atom's own B = dE_i/dA (Bk,
+// the team's LDS copy) and e = dE_i/dq (ei), the radial part through eps_k =
+// sum_n e_n c_R[a][b][n][k] (one direction per pair); the atom's
+// own-direction sum sum_j h_ij, its virial -sum_j r_ij (x) h_ij, and -h_ij
+// written into the slot of the reverse pair (j, i), so that k_force_gather
+// completes F_j = sum h_jk + sum (-h_kj) with contiguous reads and no atomics.
+// The teams of a wavefront walk the neighbour-species segments in lock step
+// (coefficient addresses uniform over the block).
 template <typename R, class Sh, int S>
 __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __restrict__ theta, int i, bool live,
                                            int a, const int64_t* __restrict__ row, const int* __restrict__ seg,
                                            const Rec<R>* __restrict__ pairs, const int* __restrict__ reverse,
                                            const R* Bk, const R* __restrict__ ei, Rec<R>* __restrict__ h_in,
                                            R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
-    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM;
+    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA;
     const int T = dm.T;
     const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
     int64_t p = live ? row[i] : 0;
@@ -571,97 +666,30 @@ __device__ __forceinline__ void force_pass(int lane, const Dims& dm, const R* __
                 nx = pairs[p + kn];
                 nrev = reverse[p + kn];
             }
-            const R r = sqrt(pr.x * pr.x + pr.y * pr.y + pr.z * pr.z);
-            const R ir = R(1) / r;
-            const R u[3] = {pr.x * ir, pr.y * ir, pr.z * ir};
-            R f[KR], fp[KR];
-            cheb_basis<R, KR, true>(r, rcR, irR, f, fp);
-            R sr = R(0);
-#pragma unroll
-            for (int kk = 0; kk < KR; ++kk) sr += epsk[kk] * fp[kk];
-            R hv[3] = {sr * u[0], sr * u[1], sr * u[2]};
-            if (k < ang) {
-                R fa[KA], fap[KA];
-                cheb_basis<R, KA, true>(r, rcA, irA, fa, fap);
-                R c[LM], cp[LM];
-#pragma unroll
-                for (int lm = 0; lm < LM; ++lm) c[lm] = cp[lm] = R(0);
-#pragma unroll
-                for (int n = 0; n < NA; ++n) {
-                    R g = R(0), gp = R(0);
-#pragma unroll
-                    for (int kk = 0; kk < KA; ++kk) {
-                        g += cA[n * KA + kk] * fa[kk];
-                        gp += cA[n * KA + kk] * fap[kk];
-                    }
-#pragma unroll
-                    for (int lm = 0; lm < LM; ++lm) {
-                        c[lm] += Bk[n * LM + lm] * g;
-                        cp[lm] += Bk[n * LM + lm] * gp;
-                    }
-                }
-                // G = grad_u sum_lm c_lm Y_lm(u); Y_lm is homogeneous of degree l, so
-                // u . G = sum_lm l c_lm Y_lm (Euler) and the tangential part of
-                // the gradient is G - (u . G) u.
-                R Y[LM], G[3];
-                solid_harmonics<R, R, Sh::L>(u[0], u[1], u[2], Y);
-                R sY = R(0);
-#pragma unroll
-                for (int lm = 0; lm < LM; ++lm) sY += cp[lm] * Y[lm];
-                solid_harmonics_grad<R, Sh::L>(u[0], u[1], u[2], c, G);
-                const R lY = u[0] * G[0] + u[1] * G[1] + u[2] * G[2];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) hv[d] += sY * u[d] + (G[d] - lY * u[d]) * ir;
-            }
-            if (q >= 0) {
-                Rec<R> ho;
-                ho.x = -hv[0];
-                ho.y = -hv[1];
-                ho.z = -hv[2];
-                ho.w = R(0);
-                h_in[q] = ho;  // -dE_i/dr_ij is the pair's contribution to F_j
-            } else {
-                // no reverse pair (|r| at the cutoff in one direction only):
-                // nothing else writes this pair's own slot
-                h_in[p + k] = Rec<R>{};
-            }
-            const R rv[3] = {pr.x, pr.y, pr.z};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) F[d] += hv[d];
-#pragma unroll
-            for (int al = 0; al < 3; ++al)
-#pragma unroll
-                for (int be = 0; be < 3; ++be) Wv[al * 3 + be] -= rv[al] * hv[be];
+            force_pair<R, Sh>(pr, q, p + k, k < ang, epsk, cA, Bk, rcR, irR, rcA, irA, h_in, F, Wv);
         }
         p += tot;
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) F[d] = team_sum<S>(F[d]);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) Wv[c] = team_sum<S>(Wv[c]);
-    if (live) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            if (d % S == lane) Fown_out[(long)i * 3 + d] = F[d];
-#pragma unroll
-        for (int c = 0; c < 9; ++c)
-            if (c % S == lane) Wat_out[(long)i * 9 + c] = Wv[c];
-    }
+    force_store<R, S>(lane, live, i, F, Wv, Fown_out, Wat_out);
 }
 
-// Forces and virials (Eq. 1) in their own sweep: each team builds its atom's
+// Forces and virials (Eq. 1) in their own sweep, the teams of a wavefront in
+// lock step over the neighbour-species segments (c^A[a][b] and c_R[a][b]
+// read at addresses uniform over the block): each team builds its atom's
 // B = dE_i/dA in LDS from the stored moments and e, then runs force_pass.
+// The FP64 sweep (its pair body held in registers with c^A in VGPRs instead
+// of scalar registers would spill).
 template <typename R, class Sh, int S>
 __global__ void __launch_bounds__(kBlock)
-k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ order, const int64_t* __restrict__ soff,
-        int Na, const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
-        const int* __restrict__ reverse, const R* __restrict__ A_in, const R* __restrict__ e_in,
-        Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
+k_force_lockstep(const Dims dm, const R* __restrict__ theta, const int* __restrict__ order,
+                 const int64_t* __restrict__ soff, int Na, const int64_t* __restrict__ row,
+                 const int* __restrict__ seg, const Rec<R>* __restrict__ pairs, const int* __restrict__ reverse,
+                 const R* __restrict__ A_in, const R* __restrict__ e_in, Rec<R>* __restrict__ h_in,
+                 R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
     constexpr int NA = Sh::NA, LM = Sh::LM, D = Sh::D;
     constexpr int TEAMS = kBlock / S;
     __shared__ R Bsh[TEAMS][NA * LM];
     const int team = threadIdx.x / S, lane = threadIdx.x % S;
-    // one species per block (uniform coefficient addresses), as in the sweeps
     int a;
     long lo = 0, hi = 0;
     species_chunk(soff, dm.T, TEAMS, xcd_tile(blockIdx.x, gridDim.x), &a, &lo, &hi);
@@ -677,6 +705,139 @@ k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ orde
     __syncthreads();
     force_pass<R, Sh, S>(lane, dm, theta, i, live, a, row, seg, pairs, reverse, Bsh[team], ei, h_in, Fown_out,
                          Wat_out);
+}
+
+// One of the force sweep's two walks over a team's row (ANG: the angular
+// pairs of every neighbour-species segment, else the radial-only pairs):
+// the walk's k-th pair lies in the segment b whose table entry is the first
+// with end > k (end: .x for the angular walk, .z for the radial one), at row
+// offset k + off (.y, .w). Lane l takes k = l, l + S, ...; the next pair's
+// segment, record and reverse index are found one iteration ahead, with no
+// branch around the loads (the last iteration reads the walk's last pair
+// again and drops it).
+template <typename R, class Sh, int S, bool ANG>
+__device__ __forceinline__ void force_walk(int lane, int total, const int4* tab, int64_t p0,
+                                           const Rec<R>* __restrict__ pairs, const int* __restrict__ reverse,
+                                           const R* cAs, int cas, const R* eps, const R* Bk, R rcR, R irR, R rcA,
+                                           R irA, Rec<R>* __restrict__ h_in, R* F, R* Wv) {
+    constexpr int KR = Sh::KR;
+    if (total <= 0) return;
+    int bn = 0;
+    int4 tn = tab[0];
+    int kn = min(lane, total - 1);
+    while (kn >= (ANG ? tn.x : tn.z)) tn = tab[++bn];
+    int64_t posn = p0 + kn + (ANG ? tn.y : tn.w);
+    Rec<R> nx = pairs[posn];
+    int nrev = reverse[posn];
+    // the first record is waited for here: left pending into the loop, the
+    // wait for it merges with the loop's own and then also covers the
+    // previous iteration's h store
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    for (int k = lane; k < total; k += S) {
+        const Rec<R> pr = nx;
+        const int q = nrev, b = bn;
+        const int64_t pos = posn;
+        kn = min(k + S, total - 1);
+        while (kn >= (ANG ? tn.x : tn.z)) tn = tab[++bn];
+        posn = p0 + kn + (ANG ? tn.y : tn.w);
+        nx = pairs[posn];
+        nrev = reverse[posn];
+        // B's reads stay in the loop (hoisted, N_A x 24 values would take
+        // registers from the occupancy): an offset opaque to the compiler
+        int bo = 0;
+        asm volatile("" : "+v"(bo));
+        force_pair<R, Sh>(pr, q, pos, ANG, eps + b * KR, cAs + b * cas, Bk + bo, rcR, irR, rcA, irA, h_in, F, Wv);
+    }
+}
+
+// Forces and virials (Eq. 1) in their own sweep. Each team builds its atom's
+// B = dE_i/dA in LDS from the stored moments and e and walks its row twice,
+// across the neighbour-species segments: first the angular pairs of every
+// segment, then the radial-only pairs. The teams of a wavefront then pad
+// only at the end of each walk instead of at the end of every segment (and
+// no wavefront runs the angular part for one team while another is on its
+// radial-only pairs). A pair's segment b selects c^A[a][b] (staged for the
+// whole block) and the team's eps_k[b] in LDS.
+template <typename R, class Sh, int S>
+__global__ void __launch_bounds__(kBlock)
+k_force(const Dims dm, const R* __restrict__ theta, const int* __restrict__ order, const int64_t* __restrict__ soff,
+        int Na, const int64_t* __restrict__ row, const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
+        const int* __restrict__ reverse, const R* __restrict__ A_in, const R* __restrict__ e_in,
+        Rec<R>* __restrict__ h_in, R* __restrict__ Fown_out, R* __restrict__ Wat_out) {
+    constexpr int NR = Sh::NR, NA = Sh::NA, KR = Sh::KR, KA = Sh::KA, LM = Sh::LM, D = Sh::D;
+    constexpr int TEAMS = kBlock / S;
+    __shared__ R Bsh[TEAMS][NA * LM];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = dm.T;
+    const ForceLds g = force_lds(T, NA, KA, KR, TEAMS, int(sizeof(R)));
+    R* cAs = reinterpret_cast<R*>(smem_raw);
+    const int team = threadIdx.x / S, lane = threadIdx.x % S;
+    R* eps = reinterpret_cast<R*>(smem_raw + g.off_eps) + team * g.eps_team;
+    int4* tab = reinterpret_cast<int4*>(smem_raw + g.off_tab) + team * (T + 1);
+    // one species per block, as in the sweeps
+    int a;
+    long lo = 0, hi = 0;
+    species_chunk(soff, T, TEAMS, xcd_tile(blockIdx.x, gridDim.x), &a, &lo, &hi);
+    if (a < 0) return;
+    const bool live = lo + team < hi;
+    const int i = live ? order[lo + team] : 0;
+    const R* __restrict__ ei = e_in + (long)i * D;
+    // c^A[a][b] for every neighbour species b
+    {
+        const R* __restrict__ cAa = theta + dm.offA + (long)(a * T) * NA * KA;
+        for (int x = threadIdx.x; x < T * NA * KA; x += kBlock) {
+            const int b = x / (NA * KA);
+            cAs[b * g.cas + (x - b * NA * KA)] = cAa[x];
+        }
+    }
+    // the team's eps_k[b] = sum_n e_n c_R[a][b][n][k], column (b, k) per lane
+    {
+        R en[NR];
+#pragma unroll
+        for (int n = 0; n < NR; ++n) en[n] = live ? ei[n] : R(0);
+        const R* __restrict__ cRa = theta + (long)(a * T) * NR * KR;
+        for (int c = lane; c < T * KR; c += S) {
+            const int b = c / KR;
+            const R* __restrict__ col = cRa + (long)b * NR * KR + (c - b * KR);
+            R sum = R(0);
+#pragma unroll
+            for (int n = 0; n < NR; ++n) sum += en[n] * col[n * KR];
+            eps[c] = sum;
+        }
+    }
+    // the team's segment table: entry b = (end of b's angular pairs in the
+    // angular walk, their row offset, end of b's radial-only pairs in the
+    // radial walk, their row offset); entry T = the two walks' lengths
+    if (lane == 0) {
+        int preA = 0, preR = 0, rel = 0;
+        for (int b = 0; b < T; ++b) {
+            const int tot = live ? seg[(i * T + b) * 2] : 0;
+            const int ang = live ? seg[(i * T + b) * 2 + 1] : 0;
+            tab[b] = make_int4(preA + ang, rel - preA, preR + (tot - ang), rel + ang - preR);
+            preA += ang;
+            preR += tot - ang;
+            rel += tot;
+        }
+        tab[T] = make_int4(preA, preR, 0, 0);
+    }
+    if (live) {
+        moment_adjoints<R, Sh, S, false>(lane, A_in + (long)i * NA * LM, nullptr, ei, nullptr, Bsh[team], nullptr);
+    } else {
+        for (int x = lane; x < NA * LM; x += S) Bsh[team][x] = R(0);
+    }
+    __syncthreads();
+    const R rcR = R(dm.rcR), rcA = R(dm.rcA), irR = R(1.0 / dm.rcR), irA = R(1.0 / dm.rcA);
+    const int64_t p0 = live ? row[i] : 0;
+    const int4 len = tab[T];
+    R F[3] = {R(0), R(0), R(0)};
+    R Wv[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Wv[c] = R(0);
+    force_walk<R, Sh, S, true>(lane, len.x, tab, p0, pairs, reverse, cAs, g.cas, eps, Bsh[team], rcR, irR, rcA, irA,
+                               h_in, F, Wv);
+    force_walk<R, Sh, S, false>(lane, len.y, tab, p0, pairs, reverse, cAs, g.cas, eps, Bsh[team], rcR, irR, rcA,
+                                irA, h_in, F, Wv);
+    force_store<R, S>(lane, live, i, F, Wv, Fown_out, Wat_out);
 }
 
 // F_i = (own-direction sum) + sum_{p in row i} h_in[p]: team of S lanes per

@@ -97,10 +97,23 @@ nep_status run_shape(const Ctx& c) {
     if (c.mode == Mode::Forward || loss) {
         if (Na > 0 && (rs = with_team(c.plan.team_force, [&](auto S_) -> nep_status {
                 constexpr int S = decltype(S_)::value;
-                if (!fused_force)
-                    NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0, st, dm,
+                if (fused_force) {
+                } else if constexpr (sizeof(R) == 8) {
+                    NEP_LAUNCH("force", (k_force_lockstep<R, Sh, S>), dim3(team_grid(S) + dm.T), dim3(kBlock), 0,
+                               st, dm, theta, c.species_order, c.species_offset, Na, c.row, c.seg, pairs, c.reverse,
+                               Wr(L.A), Wr(L.e), hslots, Wr(L.Fown), Wr(L.Wat));
+                } else {
+                    // the segment-crossing force sweep: c^A, eps_k and the segment
+                    // tables in dynamic LDS
+                    const size_t shm = force_lds(dm.T, Sh::NA, Sh::KA, Sh::KR, kBlock / S, int(sizeof(R))).bytes;
+                    const size_t stat = size_t(kBlock / S) * Sh::NA * Sh::LM * sizeof(R);
+                    if (shm + stat > 64 * 1024)
+                        NEP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force<R, Sh, S>),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
+                    NEP_LAUNCH("force", (k_force<R, Sh, S>), dim3(team_grid(S) + dm.T), dim3(kBlock), shm, st, dm,
                                theta, c.species_order, c.species_offset, Na, c.row, c.seg, pairs, c.reverse, Wr(L.A),
                                Wr(L.e), hslots, Wr(L.Fown), Wr(L.Wat));
+                }
                 NEP_LAUNCH("force_gather", (k_force_gather<R, S>), dim3(team_grid(S)), dim3(kBlock), 0, st, Na,
                            c.row, reinterpret_cast<const Rec<R>*>(Wr(L.h)), Wr(L.Fown), F);
                 return NEP_OK;
