@@ -2068,6 +2068,11 @@ k_network_backward(const Dims dm, const R* __restrict__ theta, const R* __restri
 template <typename R>
 struct LaneNet {
     static constexpr int MC = sizeof(R) == 4 ? 32 : 16;  // hidden units per LDS tile
+    // the backward pass stages three outputs per unit: half the units per
+    // tile keep its LDS (13 KB per FP32 wavefront) from capping the waves
+    // per SIMD below what its registers allow
+    static constexpr int MCB = MC / 2;
+    static_assert((MC & (MC - 1)) == 0 && (MCB & (MCB - 1)) == 0, "unit tiles of a power of two");
 };
 
 template <typename R, class Sh>
@@ -2112,9 +2117,11 @@ k_network_forward_lane(const Dims dm, const R* __restrict__ theta, const R* __re
             tb[l * (MC + 1) + m] = t;
         }
         __syncthreads();
-        for (int x = l; x < nat * mn; x += 64) {
-            const int sl = x / mn, m = x % mn;
-            t_out[(lo + sl) * H + mu0 + m] = tb[sl * (MC + 1) + m];
+        // element x of the tile is unit x % MC of atom x / MC (MC a power of
+        // two: shifts, no division); units past the layer's end are skipped
+        for (int x = l; x < nat * MC; x += 64) {
+            const int sl = x / MC, m = x % MC;
+            if (m < mn) t_out[(lo + sl) * H + mu0 + m] = tb[sl * (MC + 1) + m];
         }
         __syncthreads();
     }
@@ -2132,7 +2139,7 @@ k_network_backward_lane(const Dims dm, const R* __restrict__ theta, const R* __r
                         const R* __restrict__ dq_in, const R* __restrict__ e_in, const R* __restrict__ t_in,
                         R* __restrict__ abar_out, R* __restrict__ alpha_out, R* __restrict__ beta_out,
                         R* __restrict__ gamma_out) {
-    constexpr int D = Sh::D, MC = LaneNet<R>::MC, LD = MC + 1;
+    constexpr int D = Sh::D, MC = LaneNet<R>::MCB, LD = MC + 1;
     __shared__ R tb[3][64 * LD];
     const int T = dm.T, H = dm.H;
     int a;
@@ -2152,38 +2159,40 @@ k_network_backward_lane(const Dims dm, const R* __restrict__ theta, const R* __r
         dk[v] = qscale[v] * dq_in[ia * D + v];
         z[v] = R(0);
     }
-    const R* __restrict__ trow = t_in + (lo + (live ? l : 0)) * H;
     for (int mu0 = 0; mu0 < H; mu0 += MC) {
         const int mn = H - mu0 < MC ? H - mu0 : MC;
-        // the lane's own activations of the tile's units, all loads in flight
-        // at once (units past the layer's end read unit mu0 and are unused)
-        R tv[MC];
-#pragma unroll
-        for (int m = 0; m < MC; ++m) tv[m] = trow[mu0 + (m < mn ? m : 0)];
-#pragma unroll
-        for (int m = 0; m < MC; ++m) {
-            if (m < mn) {
-                const R* __restrict__ w = W0 + (long)(mu0 + m) * D;
-                R da = R(0);
-#pragma unroll
-                for (int v = 0; v < D; ++v) da += w[v] * dk[v];
-                const R t = live ? tv[m] : R(0);
-                const R sp = R(1) - t * t, wm = w1[mu0 + m];
-                tb[0][l * LD + m] = wm * sp * (eb - R(2) * t * da);
-                tb[1][l * LD + m] = wm * sp;
-                tb[2][l * LD + m] = eb * t + sp * da;
-                const R c2 = R(-2) * wm * t * sp * da;
-#pragma unroll
-                for (int v = 0; v < D; ++v) z[v] += w[v] * c2;
-            }
+        // the tile's activations t[atom][unit], read along the atoms' rows
+        // (coalesced) into the gamma tile, whose slot each unit overwrites
+        // after reading it; the unit loop then stays rolled, so each weight
+        // row arrives in a few wide scalar loads
+        for (int x = l; x < nat * MC; x += 64) {
+            const int sl = x / MC, m = x % MC;
+            if (m < mn) tb[2][sl * LD + m] = t_in[(lo + sl) * H + mu0 + m];
         }
         __syncthreads();
-        for (int x = l; x < nat * mn; x += 64) {
-            const int sl = x / mn, m = x % mn;
-            const long o = (lo + sl) * H + mu0 + m;
-            alpha_out[o] = tb[0][sl * LD + m];
-            beta_out[o] = tb[1][sl * LD + m];
-            gamma_out[o] = tb[2][sl * LD + m];
+        for (int m = 0; m < mn; ++m) {
+            const R* __restrict__ w = W0 + (long)(mu0 + m) * D;
+            R da = R(0);
+#pragma unroll
+            for (int v = 0; v < D; ++v) da += w[v] * dk[v];
+            const R t = live ? tb[2][l * LD + m] : R(0);
+            const R sp = R(1) - t * t, wm = w1[mu0 + m];
+            tb[0][l * LD + m] = wm * sp * (eb - R(2) * t * da);
+            tb[1][l * LD + m] = wm * sp;
+            tb[2][l * LD + m] = eb * t + sp * da;
+            const R c2 = R(-2) * wm * t * sp * da;
+#pragma unroll
+            for (int v = 0; v < D; ++v) z[v] += w[v] * c2;
+        }
+        __syncthreads();
+        for (int x = l; x < nat * MC; x += 64) {
+            const int sl = x / MC, m = x % MC;
+            if (m < mn) {
+                const long o = (lo + sl) * H + mu0 + m;
+                alpha_out[o] = tb[0][sl * LD + m];
+                beta_out[o] = tb[1][sl * LD + m];
+                gamma_out[o] = tb[2][sl * LD + m];
+            }
         }
         __syncthreads();
     }
