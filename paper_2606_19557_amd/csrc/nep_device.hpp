@@ -435,11 +435,15 @@ struct MomentExchange {
 // modulo 32, so the broadcast reads of different teams spread over the banks),
 // and the bytes of one wavefront's LDS: its accumulator G[T][N_A][K_A] for one
 // atom species, the slots, and per team the segment table (angular starts
-// [T+1], row offsets [T]). Host and device use the same function.
+// [T+1], row offsets [T]), and the atom order of the wavefront's current
+// group of up to kCgSortTiles tiles. Host and device use the same function.
 struct CgRowsGeom {
     int S, teams, vec, kfp, slot, tstride;
-    size_t off_slots, off_tab, wave_bytes;
+    size_t off_slots, off_tab, off_perm, wave_bytes;
 };
+// Tiles per group whose atoms the row-owned coefficient sweep orders by their
+// angular pair counts before cutting them into tiles again.
+constexpr int kCgSortTiles = 8;
 // Bank-conflict count of one wavefront's 16-byte LDS accesses to the slots:
 // lane (team t, lane q) writes its own slot at t*ts + q*slot and every lane
 // of team t reads one slot of its team, chunk by chunk (all sizes in 4-byte
@@ -497,7 +501,8 @@ __host__ __device__ constexpr CgRowsGeom cg_rows_place(CgRowsGeom g, int T, int 
     const size_t G = size_t(T) * NA * KA * rbytes;
     g.off_slots = (G + 15) / 16 * 16;
     g.off_tab = g.off_slots + size_t(g.teams) * g.tstride * rbytes;
-    g.wave_bytes = (g.off_tab + size_t(g.teams) * (2 * T + 1) * 4 + 15) / 16 * 16;
+    g.off_perm = (g.off_tab + size_t(g.teams) * (2 * T + 1) * 4 + 15) / 16 * 16;
+    g.wave_bytes = (g.off_perm + size_t(kCgSortTiles) * g.teams * 4 + 15) / 16 * 16;
     return g;
 }
 __host__ __device__ constexpr CgRowsGeom cg_rows_geom(int T, int NA, int KA, int LM, int rbytes, int rows) {

@@ -1347,7 +1347,7 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
                           const int* __restrict__ seg, const Rec<R>* __restrict__ pairs,
                           const R* __restrict__ ubar, const double* __restrict__ Ubar, const R* __restrict__ A_in,
                           const R* __restrict__ dA_in, const R* __restrict__ e_in, const R* __restrict__ abar,
-                          double* __restrict__ partial) {
+                          int group_tiles, double* __restrict__ partial) {
     constexpr int NA = Sh::NA, KA = Sh::KA, LM = Sh::LM, L = Sh::L, D = Sh::D;
     constexpr CgRowsGeom GM = cg_rows_slots(NA, KA, LM, int(sizeof(R)), ROWS);
     constexpr int S = GM.S, TEAMS = GM.teams, VEC = GM.vec, KFP = GM.kfp, SLOT = GM.slot, TSTRIDE = GM.tstride;
@@ -1376,6 +1376,19 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
     const int gw = blockIdx.x * nw + wave, GW = gridDim.x * nw;
     const int tiles_ub = (Na + TEAMS - 1) / TEAMS + T;
     const int per_wave = (tiles_ub + GW - 1) / GW;
+    const int wave_end = min((gw + 1) * per_wave, tiles_ub);
+    // With group_tiles > 0 (at most kCgSortTiles), the atoms of a group of up
+    // to group_tiles consecutive tiles of one species are ordered by their
+    // angular pair counts (largest first, ties in species order), then cut
+    // into tiles again: the teams of a tile then have similar pair counts
+    // and pad less at the end of their atoms. The group's tiles keep their
+    // sizes and species; perm holds the order, keys (in the slots, free
+    // between tiles) the counts. With 0 the tiles keep the species order.
+    int* perm = reinterpret_cast<int*>(wbase + gm.off_perm);
+    int* keys = reinterpret_cast<int*>(wbase + gm.off_slots);
+    static_assert(size_t(kCgSortTiles) * TEAMS * 4 <= size_t(TEAMS) * TSTRIDE * sizeof(R), "keys fit the slots");
+    int group_end = -1;
+    long group_lo = 0;
     double* __restrict__ prow = partial + (long)gw * T * G_len;
     unsigned met = 0;  // species whose section this wavefront has written
     int cur_a = -1;
@@ -1398,11 +1411,39 @@ k_angular_coeff_grad_rows(const Dims dm, const int* __restrict__ order, const in
             flush_species();
             cur_a = a;
         }
+        if (group_tiles > 0 && tile >= group_end) {
+            // a new group: this tile and the next ones of species a in the
+            // wavefront's range, at most kCgSortTiles
+            const long a_hi = soff[a + 1];
+            const int left = int((a_hi - lo + TEAMS - 1) / TEAMS);
+            const int nt = min(min(group_tiles, left), wave_end - tile);
+            const int n = int(min(a_hi, lo + long(nt) * TEAMS) - lo);
+            group_end = tile + nt;
+            group_lo = lo;
+            for (int x = wl; x < n; x += 64) {
+                const int ii = order[lo + x];
+                int c = 0;
+                for (int b = 0; b < T; ++b) c += seg[((long)ii * T + b) * 2 + 1];
+                keys[x] = c;
+            }
+            X::wave_fence();
+            for (int x = wl; x < n; x += 64) {
+                const int kx = keys[x];
+                int rk = 0;
+                for (int y = 0; y < n; ++y) {
+                    const int ky = keys[y];
+                    rk += (ky > kx || (ky == kx && y < x)) ? 1 : 0;
+                }
+                perm[rk] = order[lo + x];
+            }
+            X::wave_fence();
+        }
         const bool live = in_team && lo + team < hi;
         // The atom's data: every lane loads (a lane without an atom reads the
         // tile's first one, lo < hi, and drops what it read), so that the loads
         // go out together rather than one after another behind branches.
-        const int i = order[live ? lo + team : lo];
+        const int k0 = int(lo - group_lo);
+        const int i = group_tiles > 0 ? perm[k0 + (live ? team : 0)] : order[live ? lo + team : lo];
         const int s = atom_struct[i];
         const int64_t p0 = row[i];
         R ui[3], U[9];

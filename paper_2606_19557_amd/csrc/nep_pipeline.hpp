@@ -173,10 +173,15 @@ nep_status run_shape(const Ctx& c) {
                     if (resident < 0) return fail(NEP_ERR_HIP, "occupancy query of the coefficient sweep failed");
                     const int grid = std::max(1, std::min(L.ang_rows / cg_rows_nw, resident));
                     ang_rows_used = grid * cg_rows_nw;
+                    // atoms ordered by angular pair count within groups of tiles
+                    // when a wavefront walks enough tiles to amortise the ordering
+                    const long tiles_ub = (long(Na) + cg_rows_gm.teams - 1) / cg_rows_gm.teams + dm.T;
+                    const long per_wave = (tiles_ub + ang_rows_used - 1) / ang_rows_used;
+                    const int group_tiles = per_wave >= 4 ? kCgSortTiles : 0;
                     NEP_LAUNCH("angular_coeff_grad", (k_angular_coeff_grad_rows<R, Sh, ROWS>),
                                dim3(grid), dim3(64 * cg_rows_nw), shm, st, dm, c.species_order,
                                c.species_offset, c.atom_struct, Na, c.row, c.seg, pairs, Wr(L.ubar), Wd(L.Ubar),
-                               Wr(L.A), Wr(L.dA), Wr(L.e), Wr(L.abar), Wd(L.ang_part));
+                               Wr(L.A), Wr(L.dA), Wr(L.e), Wr(L.abar), group_tiles, Wd(L.ang_part));
                     return NEP_OK;
                 })))
                 return rs;
