@@ -43,9 +43,13 @@ def test_nep44_param_count_is_table2():
     assert P == 70401 and D == 35
 
 
+# f32-force4: the force sweep with 4-lane teams, 64 atoms per block, whose
+# per-team radial coefficients and segment tables for 16 species take more
+# than 64 KB of LDS beside the static B blocks
 @pytest.mark.parametrize("dtype,plan", [("f64", None), ("f32", None), ("f32", N.Plan(network=3, coeff_grad_rows=2)),
-                                        ("f32", N.Plan(4, 16, 8, 32, 7, 16, 1))],
-                         ids=["f64", "f32", "f32-rows2", "f32-teams"])
+                                        ("f32", N.Plan(4, 16, 8, 32, 7, 16, 1)),
+                                        ("f32", N.Plan(team_force=4, network=2))],
+                         ids=["f64", "f32", "f32-rows2", "f32-teams", "f32-force4"])
 def test_sixteen_species_parity(dtype, plan):
     print(f"16 species {dtype} {plan}", flush=True)
     md, m, b, th, s, tg = fixture(NEP44, seed=44, batch=_batch())
