@@ -729,9 +729,10 @@ __device__ __forceinline__ void force_walk(int lane, int total, const int4* tab,
     int64_t posn = p0 + kn + (ANG ? tn.y : tn.w);
     Rec<R> nx = pairs[posn];
     int nrev = reverse[posn];
-    // the first record is waited for here: left pending into the loop, the
-    // wait for it merges with the loop's own and then also covers the
-    // previous iteration's h store
+    // a wait for all vector memory at the walk's start: the compiler merges
+    // its wait counts where the loop is entered, and without this wait the
+    // merged count made every iteration begin by waiting for the previous
+    // pair's h store; with it, that wait comes after the pair's arithmetic
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     for (int k = lane; k < total; k += S) {
         const Rec<R> pr = nx;
